@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Benchmark of the swarm evaluation of 3DPIFCM on one MI355X.
+
+Workload "ragged6-swarm64": six random-ellipsoid volumes with X, Y uniform in
+64..256 and Z in 64..128 (seed 4), 64 particles (lambda, xi) ~ U[0,1)^2
+(seed 104) shared by all volumes, C = 4, m = 2, the 3x3x3 neighbourhood,
+20 IFCM iterations per (volume, particle) (eps = 0), from each volume's FCM
+initial state.  One step = normalise the six raw volumes and evaluate the
+whole swarm (iteration invariants, 20 fused iterations per pair, the final
+objective) with the batched launch.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Prints one JSON line: throughput in voxel-cluster-iterations per second,
+the roofline of the dominant kernel (the fused step) from HIP events on the
+stream it runs on, the same workload through one launch per particle, and
+the FP64 oracle's rate on a bounded sample of the workload on this host.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel-cluster-iters/s + HBM GB/s; batched swarm vs plain per-particle on 1 GPU"
+HBM_PEAK_GBPS = 8000.0
+KERNEL = "k_ifcm_gather<4, m=2, TY=4, step>"
+KERNEL_SOURCES = ("paper_2002_01981_amd/csrc/gather.h", "paper_2002_01981_amd/csrc/common.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ifcm_gather_ragged6-swarm64_traffic.json")
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(vol_raw, iters):
+    """The FP64 oracle, as it stands, on one (volume, particle) pair of the
+    workload for `iters` iterations on this host's cores."""
+    import numpy as np
+    import oracle
+    x = oracle.normalize(vol_raw)
+    p = oracle.Params(C=4, m=2.0, eps=0.0, max_iter=1)
+    c = np.array([0.125, 0.375, 0.625, 0.875])
+    U = oracle.init_memberships(x, c, p)
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        U, c, _ = oracle.step(x, U, c, p, 0.3, 0.4)
+    dt = time.perf_counter() - t0
+    return x.size * 4 * iters / dt, dt, oracle.get_threads()
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--mode", choices=("batched", "plain"), default="batched")
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-particle leg")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a device copy of MIB MiB a few times (counter scaling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2002_01981_amd import (PIFCM_SWARM_BATCHED, PIFCM_SWARM_PLAIN, Context,
+                                      Params)
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {args.calibrate_copy} MiB x5")
+        return
+
+    W = synth.WORKLOADS["ragged6-swarm64"]
+    T, P, C = W["iters"], W["particles"], W["C"]
+    dims = synth.ragged_dims(W["seed"], W["count"])
+    log(f"workload ragged6-swarm64: volumes {dims}, {P} particles, {T} iterations")
+    vols = synth.ragged_batch(seed=W["seed"], count=W["count"], sigma=W["sigma"], dims=dims)
+    raws = [torch.from_numpy(r).cuda() for r, _ in vols]
+    xs = [torch.empty_like(r) for r in raws]
+    ctx = Context(0)
+    init_p = Params(C=C, m=W["m"], eps=1e-5, max_iter=50)
+    c0s, U0s = [], []
+    for r, x in zip(raws, xs):
+        ctx.pifcm_normalize(r, out=x)
+        c, U0, _ = ctx.pifcm_fcm_init(x, init_p)
+        c0s.append(c)
+        U0s.append(U0)
+    c0s = np.stack(c0s)
+    parts = synth.uniform_particles(W["particle_seed"], P)
+    particles = np.ascontiguousarray(np.broadcast_to(parts, (len(xs), P, 2)))
+    p = Params(C=C, m=W["m"], eps=W["eps"], max_iter=T)
+    nvox = [int(np.prod(d)) for d in dims]
+    work = sum(nvox) * C * T * P           # voxel-cluster-iterations per step
+    mode = PIFCM_SWARM_BATCHED if args.mode == "batched" else PIFCM_SWARM_PLAIN
+
+    def step(m=mode):
+        for r, x in zip(raws, xs):
+            ctx.pifcm_normalize(r, out=x)
+        return ctx.swarm_evaluate(xs, p, particles, c0s, U0s, mode=m)
+
+    for i in range(args.warmup):
+        out = step()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    assert np.all(out["iters"] == T) if args.warmup else True
+    torch.cuda.synchronize()
+    ctx.pifcm_get_timing(reset=True)
+    ctx.pifcm_set_timing(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.pifcm_set_timing(False)
+    kern_ms, launches = ctx.pifcm_get_timing(reset=True)
+    log(f"timed {args.steps} steps in {t1 - t0:.3f}s")
+    assert np.all(out["iters"] == T) and np.all(np.isfinite(out["fitness"]))
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = work / (ms_step * 1e-3)
+
+    # Roofline of the fused step: algorithmic bytes per launch = per voxel and
+    # particle, U^(t) read (4C B) + U^(t+1) written (4C B) + x read (4 B).
+    per_launch_bytes = sum(nvox) * P * (8 * C + 4)
+    avg_launch_ms = kern_ms / max(launches, 1)
+    achieved = per_launch_bytes / (avg_launch_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == "ragged6-swarm64":
+            traffic = tr.get("hbm_bytes_per_launch")
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=traffic,
+                    kernel=KERNEL, avg_launch_us=round(avg_launch_ms * 1e3, 2),
+                    launches=int(launches), algorithmic_bytes_per_launch=per_launch_bytes)
+
+    plain = None
+    if not args.no_plain and mode == PIFCM_SWARM_BATCHED:
+        step(PIFCM_SWARM_PLAIN)
+        torch.cuda.synchronize()
+        ctx.pifcm_set_timing(True)
+        tp0 = time.perf_counter()
+        outp = step(PIFCM_SWARM_PLAIN)
+        torch.cuda.synchronize()
+        tp1 = time.perf_counter()
+        ctx.pifcm_set_timing(False)
+        pk_ms, pl = ctx.pifcm_get_timing(reset=True)
+        same = bool(np.array_equal(outp["fitness"], out["fitness"]))
+        plain = dict(ms_per_step=round((tp1 - tp0) * 1e3, 3),
+                     value=work / (tp1 - tp0), launches_per_step=int(pl),
+                     avg_launch_us=round(pk_ms / max(pl, 1) * 1e3, 2),
+                     batched_speedup=round((tp1 - tp0) * 1e3 / ms_step, 3),
+                     bit_identical_to_batched=same)
+        log(f"plain: {(tp1 - tp0) * 1e3:.1f} ms/step, identical={same}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        b = int(np.argmin(nvox))
+        rate, dt, cores = cpu_baseline(vols[b][0], args.cpu_iters)
+        cpu = dict(value=rate, unit="voxel-cluster-iters/s", cores=cores, kind="oracle",
+                   sample=f"volume {b} ({dims[b][2]}x{dims[b][1]}x{dims[b][0]}), one particle, "
+                          f"{args.cpu_iters} iterations, {dt:.1f} s")
+        log(f"cpu baseline: {rate:.3g} vci/s on {cores} threads in {dt:.1f}s")
+
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "voxel-cluster-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "ragged6-swarm64",
+            "volumes_zyx": dims,
+            "particles": P,
+            "iterations": T,
+            "C": C, "m": W["m"], "neighbourhood": "3x3x3",
+            "mode": args.mode,
+        },
+        "hbm_GBps_algorithmic": round(achieved, 1),
+        "roofline": roofline,
+        "plain": plain,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

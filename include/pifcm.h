@@ -1,0 +1,169 @@
+/*
+ * pifcm.h -- C ABI of libpifcm: the IFCM iteration of 3DPIFCM on AMD MI355X
+ * (gfx950).
+ *
+ * The method is the one of Agranonik, Herman and Last, "Parallel 3DPIFCM
+ * Algorithm for Noisy Brain MRI Images" (arXiv 2002.01981): fuzzy c-means
+ * whose distance (section 2, eq (4)) is scaled by a feature attraction H
+ * (eqs (5), (6)) and a neighbourhood attraction F (eqs (7), (8)) gathered
+ * from each voxel's 3D neighbourhood (eq (9)), iterated between memberships
+ * (eq (2)) and centres (eq (3)) until the objective (eq (1)) settles, once per
+ * particle of a swarm search over the two weights (lambda, xi) (Algorithm 1).
+ *
+ * Conventions shared by every entry point:
+ *   - Volumes are float32, laid out [nz][ny][nx] with x fastest, already
+ *     min-max normalised to [0, 1] (pifcm_normalize does that on the GPU).
+ *   - Memberships U are float32 [N][C], voxel-major (the C values of one
+ *     voxel are contiguous), N = nx * ny * nz.  Device pointers must be
+ *     16-byte aligned.  Rows of a caller-supplied U must be memberships:
+ *     entries in [0, 1] summing to 1 (within 1e-4); otherwise the call
+ *     fails with PIFCM_E_INVALID.
+ *   - "device" pointers are HIP device memory (e.g. torch tensors'
+ *     data_ptr()); "host" pointers are ordinary CPU memory.  The caller owns
+ *     every input and output buffer; the library owns its workspace (kept in
+ *     the context and reused until pifcm_destroy).
+ *   - Work is ordered after everything already queued on the context's
+ *     stream (the stream given to pifcm_create or pifcm_set_stream) and
+ *     calls that return host outputs wait for their work to finish.
+ *   - Every function returns a pifcm_status and never aborts.  On error the
+ *     host outputs are left untouched, device outputs are unspecified,
+ *     inputs are never modified, and pifcm_last_error describes the cause.
+ *   - Results are deterministic: the same inputs give bit-identical outputs
+ *     (all sums are taken in a fixed order; no floating-point atomics).
+ */
+#ifndef PIFCM_H
+#define PIFCM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PIFCM_OK = 0,
+  PIFCM_E_INVALID = -1,     /* null/misaligned pointer, out-of-range value   */
+  PIFCM_E_NONFINITE = -2,   /* a NaN or Inf intensity                       */
+  PIFCM_E_OOM = -3,         /* workspace allocation failed                  */
+  PIFCM_E_HIP = -4,         /* HIP runtime error                            */
+  PIFCM_E_UNSUPPORTED = -5  /* valid request outside what is built          */
+} pifcm_status;
+
+typedef struct pifcm_ctx pifcm_ctx;
+
+/* Context on HIP device `device`; `hip_stream` is a hipStream_t (NULL: the
+ * device's null stream).  The context owns a private non-blocking stream for
+ * its work and orders it after / before `hip_stream` with events. */
+pifcm_status pifcm_create(int device, void* hip_stream, pifcm_ctx** out);
+void pifcm_destroy(pifcm_ctx* ctx);
+pifcm_status pifcm_set_stream(pifcm_ctx* ctx, void* hip_stream);
+/* Description of the last error on ctx (valid until the next call on ctx);
+ * "" if the last call succeeded.  Accepts NULL. */
+const char* pifcm_last_error(const pifcm_ctx* ctx);
+
+/* Readings of passages the paper leaves open (flags). */
+#define PIFCM_Q2_SQDIST 2 /* weight q (eq (8)) instead of q^2 in eq (7) */
+
+typedef struct {
+  int32_t C;        /* c: number of clusters, 2..16 (Algorithm 1 input)          */
+  float m;          /* m: fuzziness, > 1 (Algorithm 1 input)                      */
+  int32_t V;        /* v: depth = number of rings; 1 = the 3x3x3 neighbourhood   */
+  float h;          /* h: exponential decay of eq (10); unused when V == 1       */
+  float eps;        /* epsilon: stop after iteration t >= 2 once
+                       |J(t-1) - J(t-2)| <= eps * |J(t-2)|; 0 = run max_iter       */
+  int32_t max_iter; /* iteration cap, >= 0                                       */
+  int32_t flags;    /* PIFCM_* readings                                          */
+} pifcm_params;
+
+typedef struct {
+  int32_t nx, ny, nz; /* >= 1 each                                               */
+  const float* x;     /* device [nz][ny][nx], normalised intensities             */
+} pifcm_volume;
+
+/* Min-max normalisation of a raw volume (Algorithm 2, step 1):
+ * x_out = (raw - min) / (max - min), evaluated in double precision and
+ * rounded to float32; a constant volume gives zeros.  raw and x_out are
+ * device [n] and may alias.  PIFCM_E_NONFINITE if any raw value is NaN/Inf. */
+pifcm_status pifcm_normalize(pifcm_ctx* ctx, const float* raw, int64_t n, float* x_out);
+
+/* One IFCM solve at fixed (lambda, xi) -- the final step of Algorithm 1
+ * (step 11) and the unit of every fitness evaluation (steps 4-9).
+ * Starting from centres_in (host [C]) and U_in (device [N][C]; NULL means
+ * eq (2) with the attraction factor 1, i.e. FCM memberships of centres_in),
+ * iterate eqs (4)-(10), (2), (3) -- every H and F of an iteration reads that
+ * iteration's input memberships -- until the stop rule of pifcm_params or
+ * max_iter.  lambda = xi = 0 is plain FCM (eqs (1)-(3)).
+ * Outputs: U_out (device [N][C], must not alias U_in), centres_out (host
+ * [C]), labels_out (device [N] uint8 argmax_j u_ij with ties to the lowest
+ * j, or NULL), J_out (host: J of eq (1) at the final state -- the fitness),
+ * iters_out (host: iterations performed), J_hist_out (host [max_iter] or
+ * NULL: J of the input state of each iteration performed).
+ * The squared distance of eq (4) is floored at 1e-12 so eq (2) stays
+ * defined when the attraction factor is <= 0 or a voxel equals a centre.
+ * PIFCM_E_UNSUPPORTED for V > 1. */
+pifcm_status ifcm_solve(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
+                        float lambda, float xi, const float* centres_in, const float* U_in,
+                        float* U_out, float* centres_out, uint8_t* labels_out, double* J_out,
+                        int32_t* iters_out, double* J_hist_out);
+
+/* Initial state of Algorithm 1 step 2: plain FCM (lambda = xi = 0) from
+ * evenly spaced centres c_j = (j + 1/2) / C, then the centres sorted
+ * ascending with the membership columns permuted alike.  The paper seeds
+ * this with an unspecified Gaussian mixture model, which is not reproduced.
+ * Outputs: U0_out (device [N][C]), centres_out (host [C]), iters_out (host,
+ * may be NULL). */
+pifcm_status pifcm_fcm_init(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
+                            float* U0_out, float* centres_out, int32_t* iters_out);
+
+/* Fitness of every particle on every volume -- Algorithm 1 step 4.
+ * vols: host array [B] (volume b holds N_b voxels); particles: host
+ * [B][P][2] of (lambda, xi); centres0: host [B][C] and U0: host array of B
+ * device pointers [N_b][C] -- the shared initial state of volume b.  Each
+ * (b, p) runs one IFCM solve from (centres0[b], U0[b]) exactly as
+ * ifcm_solve does, and its fitness is J at the final state.
+ * Outputs (host): fitness_out [B][P] (double), centres_out [B][P][C] or
+ * NULL, iters_out [B][P] or NULL.
+ * mode PIFCM_SWARM_BATCHED runs the whole swarm as one fused launch per
+ * iteration, captured in a HIP graph; PIFCM_SWARM_PLAIN launches one kernel
+ * per (b, p) per iteration.  Both give bit-identical results.
+ * B <= 32, 1 <= P, B * P <= 65536. */
+#define PIFCM_SWARM_BATCHED 0
+#define PIFCM_SWARM_PLAIN 1
+pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
+                            const pifcm_params* p, const float* particles, int32_t P,
+                            const float* centres0, const float* const* U0, double* fitness_out,
+                            float* centres_out, int32_t* iters_out, int32_t mode);
+
+/* Gradient of J_K = J(U^K, c^K) -- eq (1) after exactly K IFCM iterations
+ * from (centres0 (host [C]), U0 (device [N][C])), U0 held constant -- with
+ * respect to lambda, xi and the initial centres, by a hand-written adjoint
+ * of the K unrolled iterations.  Memberships are kept every ckpt_every
+ * iterations (1 <= ckpt_every <= K) and recomputed segment by segment.
+ * Outputs (host): J_out, dJ_dlambda, dJ_dxi, dJ_dcentres [C]. */
+pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
+                           float lambda, float xi, const float* centres0, const float* U0,
+                           int32_t K, int32_t ckpt_every, double* J_out, double* dJ_dlambda,
+                           double* dJ_dxi, double* dJ_dcentres);
+
+/* Pick the tile shape of the fused step for these volumes by timing the
+ * candidates on the GPU; every candidate must reproduce the reference
+ * candidate's results bit for bit before it may be chosen.  The choice is
+ * kept in ctx and used by later calls with the same C, m == 2 and shapes.
+ * best_out (host, may be NULL) receives a short description. */
+pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
+                        const pifcm_params* p, int32_t P, char* best_out, int32_t best_len);
+
+/* Benchmark timing of the fused step launches.  While enabled, ifcm_solve
+ * and swarm_evaluate record HIP events on the context's own stream before
+ * their first and after their last step launch (the launches are queued back
+ * to back when eps == 0) and add the elapsed time and the number of step
+ * launches to two counters.  pifcm_get_timing reads them (host outputs;
+ * either may be NULL) and, if reset != 0, clears them. */
+pifcm_status pifcm_set_timing(pifcm_ctx* ctx, int32_t enable);
+pifcm_status pifcm_get_timing(pifcm_ctx* ctx, double* step_ms, int64_t* step_launches,
+                              int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIFCM_H */

@@ -1,0 +1,273 @@
+"""ctypes binding of libpifcm (include/pifcm.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libpifcm.so.  PyTorch provides device memory (tensors' data
+pointers) and the current HIP stream.  If the shared library is missing this
+module raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libpifcm.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "pifcm.h")
+
+PIFCM_OK = 0
+PIFCM_E_INVALID = -1
+PIFCM_E_NONFINITE = -2
+PIFCM_E_OOM = -3
+PIFCM_E_HIP = -4
+PIFCM_E_UNSUPPORTED = -5
+PIFCM_Q2_SQDIST = 2
+PIFCM_SWARM_BATCHED = 0
+PIFCM_SWARM_PLAIN = 1
+
+_STATUS = {0: "OK", -1: "INVALID", -2: "NONFINITE", -3: "OOM", -4: "HIP", -5: "UNSUPPORTED"}
+
+
+class PifcmError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"libpifcm {_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Params(ct.Structure):
+    _fields_ = [("C", ct.c_int32), ("m", ct.c_float), ("V", ct.c_int32), ("h", ct.c_float),
+                ("eps", ct.c_float), ("max_iter", ct.c_int32), ("flags", ct.c_int32)]
+
+
+class _Volume(ct.Structure):
+    _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("nz", ct.c_int32), ("x", ct.c_void_p)]
+
+
+@dataclass
+class Params:
+    """pifcm_params: C clusters, fuzziness m, depth V, decay h, stop eps,
+    iteration cap, reading flags."""
+    C: int = 4
+    m: float = 2.0
+    V: int = 1
+    h: float = 1.0
+    eps: float = 1e-5
+    max_iter: int = 50
+    flags: int = 0
+
+    def c(self):
+        return _Params(self.C, self.m, self.V, self.h, self.eps, self.max_iter, self.flags)
+
+
+def header_symbols(path=HEADER):
+    """Names of the functions declared in include/pifcm.h."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:pifcm_status|void|const char\*)\s+(\w+)\s*\(", text, re.M)))
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libpifcm.so and declare its functions.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python paper_2002_01981_amd/build.py`")
+    lib = ct.CDLL(path)
+    P, vp, i32, i64 = ct.POINTER, ct.c_void_p, ct.c_int32, ct.c_int64
+    f32, f64 = ct.c_float, ct.c_double
+    st = ct.c_int
+    lib.pifcm_create.argtypes = [ct.c_int, vp, P(vp)]
+    lib.pifcm_create.restype = st
+    lib.pifcm_destroy.argtypes = [vp]
+    lib.pifcm_destroy.restype = None
+    lib.pifcm_set_stream.argtypes = [vp, vp]
+    lib.pifcm_set_stream.restype = st
+    lib.pifcm_last_error.argtypes = [vp]
+    lib.pifcm_last_error.restype = ct.c_char_p
+    lib.pifcm_normalize.argtypes = [vp, vp, i64, vp]
+    lib.pifcm_normalize.restype = st
+    lib.ifcm_solve.argtypes = [vp, P(_Volume), P(_Params), f32, f32, P(f32), vp, vp, P(f32), vp,
+                               P(f64), P(i32), P(f64)]
+    lib.ifcm_solve.restype = st
+    lib.pifcm_fcm_init.argtypes = [vp, P(_Volume), P(_Params), vp, P(f32), P(i32)]
+    lib.pifcm_fcm_init.restype = st
+    lib.swarm_evaluate.argtypes = [vp, P(_Volume), i32, P(_Params), P(f32), i32, P(f32), P(vp),
+                                   P(f64), P(f32), P(i32), i32]
+    lib.swarm_evaluate.restype = st
+    lib.ifcm_backward.argtypes = [vp, P(_Volume), P(_Params), f32, f32, P(f32), vp, i32, i32,
+                                  P(f64), P(f64), P(f64), P(f64)]
+    lib.ifcm_backward.restype = st
+    lib.pifcm_tune.argtypes = [vp, P(_Volume), i32, P(_Params), i32, ct.c_char_p, i32]
+    lib.pifcm_tune.restype = st
+    lib.pifcm_set_timing.argtypes = [vp, i32]
+    lib.pifcm_set_timing.restype = st
+    lib.pifcm_get_timing.argtypes = [vp, P(f64), P(i64), i32]
+    lib.pifcm_get_timing.restype = st
+    _lib = lib
+    return lib
+
+
+def _fp(a):
+    return a.ctypes.data_as(ct.POINTER(ct.c_float))
+
+
+def _dp(a):
+    return a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ct.POINTER(ct.c_int32))
+
+
+def _dev(t, dtype=None):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError("expected a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t
+
+
+def _volume(x):
+    import torch
+    _dev(x, torch.float32)
+    if x.dim() != 3:
+        raise ValueError("volume must be (Z, Y, X)")
+    nz, ny, nx = x.shape
+    return _Volume(nx, ny, nz, x.data_ptr())
+
+
+class Context:
+    """A libpifcm context on one GPU, ordered on torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = load_library()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        h = ct.c_void_p()
+        rc = self.lib.pifcm_create(device, ct.c_void_p(stream.cuda_stream), ct.byref(h))
+        if rc != PIFCM_OK:
+            raise PifcmError(rc, f"pifcm_create(device={device}) failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pifcm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != PIFCM_OK:
+            msg = self.lib.pifcm_last_error(self.h)
+            raise PifcmError(rc, msg.decode() if msg else "")
+
+    def set_stream(self, stream):
+        self._check(self.lib.pifcm_set_stream(self.h, ct.c_void_p(stream.cuda_stream)))
+
+    # ------------------------------------------------------------ entry points
+    def pifcm_normalize(self, raw, out=None):
+        import torch
+        _dev(raw, torch.float32)
+        if out is None:
+            out = torch.empty_like(raw)
+        _dev(out, torch.float32)
+        self._check(self.lib.pifcm_normalize(self.h, raw.data_ptr(), raw.numel(), out.data_ptr()))
+        return out
+
+    def pifcm_fcm_init(self, x, p: Params):
+        import torch
+        vol = _volume(x)
+        U0 = torch.empty((x.numel(), p.C), dtype=torch.float32, device=x.device)
+        c = np.empty(p.C, np.float32)
+        it = np.zeros(1, np.int32)
+        self._check(self.lib.pifcm_fcm_init(self.h, ct.byref(vol), ct.byref(p.c()), U0.data_ptr(),
+                                            _fp(c), _ip(it)))
+        return c, U0, int(it[0])
+
+    def ifcm_solve(self, x, p: Params, lam, xi, centres, U_in=None, labels=False,
+                   want_hist=False, U_out=None):
+        import torch
+        vol = _volume(x)
+        c = np.ascontiguousarray(centres, np.float32)
+        if U_in is not None:
+            _dev(U_in, torch.float32)
+        if U_out is None:
+            U_out = torch.empty((x.numel(), p.C), dtype=torch.float32, device=x.device)
+        lab = torch.empty(x.numel(), dtype=torch.uint8, device=x.device) if labels else None
+        cout = np.empty(p.C, np.float32)
+        J = np.zeros(1, np.float64)
+        it = np.zeros(1, np.int32)
+        hist = np.zeros(max(1, p.max_iter), np.float64)
+        self._check(self.lib.ifcm_solve(
+            self.h, ct.byref(vol), ct.byref(p.c()), float(lam), float(xi), _fp(c),
+            None if U_in is None else U_in.data_ptr(), U_out.data_ptr(), _fp(cout),
+            None if lab is None else lab.data_ptr(), _dp(J), _ip(it),
+            _dp(hist) if want_hist else None))
+        out = dict(U=U_out, c=cout, J=float(J[0]), iters=int(it[0]))
+        if labels:
+            out["labels"] = lab
+        if want_hist:
+            out["J_hist"] = hist[: out["iters"]].copy()
+        return out
+
+    def swarm_evaluate(self, xs, p: Params, particles, centres0, U0s, mode=PIFCM_SWARM_BATCHED):
+        """xs: list of B (Z, Y, X) tensors; particles: (B, P, 2); centres0:
+        (B, C); U0s: list of B (N_b, C) tensors."""
+        B = len(xs)
+        vols = (_Volume * B)(*[_volume(x) for x in xs])
+        part = np.ascontiguousarray(particles, np.float32)
+        if part.ndim == 2:
+            part = np.ascontiguousarray(np.broadcast_to(part, (B,) + part.shape))
+        P = part.shape[1]
+        c0 = np.ascontiguousarray(centres0, np.float32).reshape(B, p.C)
+        ptrs = (ct.c_void_p * B)(*[_dev(u).data_ptr() for u in U0s])
+        fit = np.empty((B, P), np.float64)
+        cout = np.empty((B, P, p.C), np.float32)
+        it = np.empty((B, P), np.int32)
+        self._check(self.lib.swarm_evaluate(self.h, vols, B, ct.byref(p.c()), _fp(part), P, _fp(c0),
+                                            ptrs, _dp(fit), _fp(cout), _ip(it), int(mode)))
+        return dict(fitness=fit, centres=cout, iters=it)
+
+    def ifcm_backward(self, x, p: Params, lam, xi, centres0, U0, K, ckpt_every):
+        vol = _volume(x)
+        c = np.ascontiguousarray(centres0, np.float32)
+        J = np.zeros(1)
+        dl = np.zeros(1)
+        dx = np.zeros(1)
+        dc = np.zeros(p.C)
+        self._check(self.lib.ifcm_backward(self.h, ct.byref(vol), ct.byref(p.c()), float(lam),
+                                           float(xi), _fp(c), _dev(U0).data_ptr(), int(K),
+                                           int(ckpt_every), _dp(J), _dp(dl), _dp(dx), _dp(dc)))
+        return dict(J=float(J[0]), dlam=float(dl[0]), dxi=float(dx[0]), dc=dc)
+
+    def pifcm_set_timing(self, enable=True):
+        self._check(self.lib.pifcm_set_timing(self.h, 1 if enable else 0))
+
+    def pifcm_get_timing(self, reset=False):
+        ms = ct.c_double()
+        n = ct.c_int64()
+        self._check(self.lib.pifcm_get_timing(self.h, ct.byref(ms), ct.byref(n), 1 if reset else 0))
+        return ms.value, n.value
+
+    def pifcm_tune(self, xs, p: Params, P):
+        B = len(xs)
+        vols = (_Volume * B)(*[_volume(x) for x in xs])
+        buf = ct.create_string_buffer(256)
+        self._check(self.lib.pifcm_tune(self.h, vols, B, ct.byref(p.c()), int(P), buf, 256))
+        return buf.value.decode()

@@ -1,0 +1,80 @@
+// pifcm_device.h -- descriptors shared by the HIP kernels and the host
+// runtime of libpifcm (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pifcm {
+
+constexpr int kMaxC = 16;         // clusters supported
+constexpr int kMaxBatchVols = 32; // volumes in one batched launch
+constexpr int kTX = 64;           // tile width along x = one wavefront
+constexpr float kDFloor = 1e-12f; // floor of the squared distance of eq (4)
+constexpr int kFcmVoxPerThread = 8;
+
+// Device-side state of one IFCM run (one volume x one particle).
+struct alignas(64) SolveState {
+  float c[2][kMaxC];   // centres by iteration parity: c^(t) lives in c[t & 1]
+  float lam, xi;       // the particle (lambda, xi)
+  float eps;           // relative stop criterion (0: run max_iter)
+  int32_t max_iter;
+  int32_t iter;        // iterations completed
+  int32_t stop;        // 1 once the run has converged or hit max_iter
+  uint32_t counter;    // tiles of the current launch that have finished
+  int32_t pad0;
+  double J_prev1;      // J(t-1): objective of the previous iteration's input
+  double J_prev2;      // J(t-2)
+  double J_eval;       // J of the final state (fitness)
+  double* J_hist;      // optional device [max_iter]: J(t-1) of iteration t
+};
+
+// One volume of a launch.
+struct VolDev {
+  const float* x;      // [nz][ny][nx] normalised intensities
+  const float* invg;   // [nz][ny][nx] 1 / sum_k |x_i - x_k| (< 0: all equal)
+  int32_t nx, ny, nz;
+  int32_t zc;          // planes per tile
+  int32_t ntx, nty, ntz;
+  int32_t tiles;       // ntx * nty * ntz (gather kernels)
+  int32_t tiles1d;     // ceil(N / voxels per block) (pointwise kernels)
+  int32_t pad;
+};
+
+// One (volume, particle) run of a launch.
+struct PairDev {
+  const float* U0;     // U^(0)
+  float* Ua;           // U^(t) for odd t
+  float* Ub;           // U^(t) for even t >= 2
+  SolveState* st;
+  float* partials;     // [tiles][2C + 1] per-tile sums of one launch
+};
+
+// Arguments of a fused launch over volumes [0, nvol) x particles [0, P).
+// Pairs are ordered volume-major: pair (b, p) = pairs[b * P + p]; work items
+// are ordered pair-major then tile, so adjacent tiles of one pair are
+// neighbours in item order.
+struct LaunchArgs {
+  const VolDev* vols;
+  const PairDev* pairs;
+  int32_t nvol;
+  int32_t P;
+  int32_t nitems;
+  int32_t q2_sqdist;   // 1: eq (7) weight q instead of q^2
+  float m;
+  int32_t use_1d;      // items are 1D voxel blocks (pointwise kernels)
+  int32_t item_begin[kMaxBatchVols + 1];  // first item of each volume
+};
+
+__host__ __device__ inline const float* u_in_of(const PairDev& pr, int t) {
+  // Input of iteration t (1-based): U^(t-1).
+  return t == 1 ? pr.U0 : ((t & 1) ? pr.Ub : pr.Ua);
+}
+__host__ __device__ inline float* u_out_of(const PairDev& pr, int t) {
+  return (t & 1) ? pr.Ua : pr.Ub;
+}
+__host__ __device__ inline const float* u_state_of(const PairDev& pr, int T) {
+  // U^(T) after T completed iterations.
+  return T == 0 ? pr.U0 : ((T & 1) ? pr.Ua : pr.Ub);
+}
+
+}  // namespace pifcm

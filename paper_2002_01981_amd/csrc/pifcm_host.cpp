@@ -1,0 +1,760 @@
+// pifcm_host.cpp -- host runtime of libpifcm: context, argument checks,
+// workspace, the IFCM solve loop, the swarm evaluation (batched launches
+// captured in a HIP graph, or one launch per particle), the tuner, and the
+// C ABI of include/pifcm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "pifcm.h"
+#include "pifcm_device.h"
+#include "pifcm_kernels.h"
+
+using namespace pifcm;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+struct GraphCache {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<char> key;
+};
+
+struct TileShape {
+  int ty = 4;
+  int zc = 32;
+};
+
+constexpr int kChunk = 8;            // iterations between stop-flag reads
+constexpr int kMaxPairs = 65536;
+
+}  // namespace
+
+struct pifcm_ctx {
+  int device = 0;
+  hipStream_t user = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::string err;
+  int num_cu = 256;
+  DevBuf invg, ubuf, partials, states, jhist, tvol, tpair, flags;
+  void* pinned = nullptr;
+  size_t pinned_cap = 0;
+  GraphCache graph;
+  bool timing = false;
+  hipEvent_t tm0 = nullptr, tm1 = nullptr;
+  double step_ms = 0.0;
+  int64_t step_launches = 0;
+  std::map<std::tuple<int, int, int, int, int>, TileShape> tuned;  // (C, m2, nx, ny, nz)
+};
+
+namespace {
+
+pifcm_status fail(pifcm_ctx* ctx, pifcm_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  return st;
+}
+
+#define HIPCHK(call)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) return fail(ctx, PIFCM_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+pifcm_status ensure(pifcm_ctx* ctx, DevBuf& b, size_t bytes, const char* what) {
+  if (bytes == 0) bytes = 256;
+  if (b.cap >= bytes) return PIFCM_OK;
+  if (b.p) {
+    HIPCHK(hipStreamSynchronize(ctx->s));
+    HIPCHK(hipFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, PIFCM_E_OOM, "cannot allocate %zu bytes of workspace for %s", bytes, what);
+  }
+  b.p = p;
+  b.cap = bytes;
+  return PIFCM_OK;
+}
+
+pifcm_status ensure_pinned(pifcm_ctx* ctx, size_t bytes) {
+  if (ctx->pinned_cap >= bytes) return PIFCM_OK;
+  if (ctx->pinned) {
+    HIPCHK(hipStreamSynchronize(ctx->s));
+    HIPCHK(hipHostFree(ctx->pinned));
+    ctx->pinned = nullptr;
+    ctx->pinned_cap = 0;
+  }
+  if (hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->pinned = nullptr;
+    return fail(ctx, PIFCM_E_OOM, "cannot allocate %zu bytes of pinned host memory", bytes);
+  }
+  ctx->pinned_cap = bytes;
+  return PIFCM_OK;
+}
+
+#define TRY(expr)                       \
+  do {                                  \
+    pifcm_status s_ = (expr);           \
+    if (s_ != PIFCM_OK) return s_;      \
+  } while (0)
+
+pifcm_status begin(pifcm_ctx* ctx) {
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipEventRecord(ctx->ev_in, ctx->user));
+  HIPCHK(hipStreamWaitEvent(ctx->s, ctx->ev_in, 0));
+  return PIFCM_OK;
+}
+
+pifcm_status finish(pifcm_ctx* ctx) {
+  HIPCHK(hipEventRecord(ctx->ev_out, ctx->s));
+  HIPCHK(hipStreamWaitEvent(ctx->user, ctx->ev_out, 0));
+  return PIFCM_OK;
+}
+
+pifcm_status timing_begin(pifcm_ctx* ctx) {
+  if (ctx->timing) HIPCHK(hipEventRecord(ctx->tm0, ctx->s));
+  return PIFCM_OK;
+}
+
+pifcm_status timing_end(pifcm_ctx* ctx) {
+  if (ctx->timing) HIPCHK(hipEventRecord(ctx->tm1, ctx->s));
+  return PIFCM_OK;
+}
+
+// After the stream has been synchronised: add the bracketed time.
+pifcm_status timing_collect(pifcm_ctx* ctx, int64_t launches) {
+  if (!ctx->timing || launches <= 0) return PIFCM_OK;
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, ctx->tm0, ctx->tm1));
+  ctx->step_ms += ms;
+  ctx->step_launches += launches;
+  return PIFCM_OK;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+pifcm_status check_params(pifcm_ctx* ctx, const pifcm_params* p) {
+  if (!p) return fail(ctx, PIFCM_E_INVALID, "params is NULL");
+  if (p->C < 2 || p->C > kMaxC) return fail(ctx, PIFCM_E_INVALID, "C = %d outside [2, %d]", p->C, kMaxC);
+  if (!std::isfinite(p->m) || !(p->m > 1.f)) return fail(ctx, PIFCM_E_INVALID, "m = %g must be finite and > 1", p->m);
+  if (p->V < 1) return fail(ctx, PIFCM_E_INVALID, "V = %d must be >= 1", p->V);
+  if (!std::isfinite(p->h) || !(p->h > 0.f)) return fail(ctx, PIFCM_E_INVALID, "h = %g must be finite and > 0", p->h);
+  if (!std::isfinite(p->eps) || p->eps < 0.f) return fail(ctx, PIFCM_E_INVALID, "eps = %g must be finite and >= 0", p->eps);
+  if (p->max_iter < 0 || p->max_iter > 1000000) return fail(ctx, PIFCM_E_INVALID, "max_iter = %d outside [0, 1e6]", p->max_iter);
+  if (p->flags & ~PIFCM_Q2_SQDIST) return fail(ctx, PIFCM_E_INVALID, "unknown flags 0x%x", p->flags);
+  if (p->V > 1) return fail(ctx, PIFCM_E_UNSUPPORTED, "V = %d: only the 3x3x3 neighbourhood (V = 1) is built", p->V);
+  return PIFCM_OK;
+}
+
+pifcm_status check_volume(pifcm_ctx* ctx, const pifcm_volume* v) {
+  if (!v) return fail(ctx, PIFCM_E_INVALID, "volume is NULL");
+  if (!v->x) return fail(ctx, PIFCM_E_INVALID, "volume intensities are NULL");
+  if (v->nx < 1 || v->ny < 1 || v->nz < 1)
+    return fail(ctx, PIFCM_E_INVALID, "volume dims %d x %d x %d must be >= 1", v->nx, v->ny, v->nz);
+  const double n = (double)v->nx * v->ny * v->nz;
+  if (n > 4.0e9) return fail(ctx, PIFCM_E_INVALID, "volume of %.0f voxels is too large", n);
+  return PIFCM_OK;
+}
+
+size_t nvox(const pifcm_volume& v) { return (size_t)v.nx * v.ny * v.nz; }
+
+TileShape shape_for(pifcm_ctx* ctx, int C, bool m2, const pifcm_volume& v) {
+  auto it = ctx->tuned.find(std::make_tuple(C, (int)m2, v.nx, v.ny, v.nz));
+  if (it != ctx->tuned.end()) return it->second;
+  TileShape t;
+  t.ty = 4;
+  t.zc = std::min(v.nz, 32);
+  return t;
+}
+
+VolDev make_vol(const pifcm_volume& v, const float* invg, TileShape ts) {
+  VolDev d{};
+  d.x = v.x;
+  d.invg = invg;
+  d.nx = v.nx;
+  d.ny = v.ny;
+  d.nz = v.nz;
+  d.zc = std::max(1, std::min(ts.zc, v.nz));
+  d.ntx = (v.nx + kTX - 1) / kTX;
+  d.nty = (v.ny + ts.ty - 1) / ts.ty;
+  d.ntz = (v.nz + d.zc - 1) / d.zc;
+  d.tiles = d.ntx * d.nty * d.ntz;
+  const size_t per = (size_t)256 * kFcmVoxPerThread;
+  d.tiles1d = (int)((nvox(v) + per - 1) / per);
+  return d;
+}
+
+int grid_for(pifcm_ctx* ctx, int nitems, int occupancy) {
+  const long resident = (long)occupancy * ctx->num_cu;
+  long g;
+  if (nitems <= 8 * resident) g = ((long)nitems + 7) / 8 * 8;
+  else g = resident / 8 * 8;
+  return (int)std::max<long>(8, g);
+}
+
+// Set up invariants of `nv` volumes into ctx->invg (concatenated) and check
+// intensities; optionally check rows of caller U0 pointers.
+pifcm_status prepare_volumes(pifcm_ctx* ctx, const pifcm_volume* vols, int nv, int C,
+                             const float* const* U0s, std::vector<size_t>& invg_off) {
+  size_t total = 0;
+  invg_off.resize(nv);
+  for (int b = 0; b < nv; ++b) {
+    invg_off[b] = total;
+    total += (nvox(vols[b]) + 63) / 64 * 64;
+  }
+  TRY(ensure(ctx, ctx->invg, total * sizeof(float), "iteration invariants"));
+  TRY(ensure(ctx, ctx->flags, 64, "flags"));
+  int* flags = (int*)ctx->flags.p;
+  HIPCHK(hipMemsetAsync(flags, 0, 64, ctx->s));
+  float* invg = (float*)ctx->invg.p;
+  for (int b = 0; b < nv; ++b) {
+    HIPCHK(launch_invariants(vols[b].x, invg + invg_off[b], vols[b].nx, vols[b].ny, vols[b].nz,
+                             flags, ctx->s));
+    if (U0s && U0s[b]) HIPCHK(launch_check_rows(U0s[b], nvox(vols[b]), C, flags + 1, ctx->s));
+  }
+  TRY(ensure_pinned(ctx, 4096));
+  HIPCHK(hipMemcpyAsync(ctx->pinned, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->s));
+  HIPCHK(hipStreamSynchronize(ctx->s));
+  const int* hf = (const int*)ctx->pinned;
+  if (hf[0]) return fail(ctx, PIFCM_E_NONFINITE, "a volume holds a NaN or Inf intensity");
+  if (hf[1])
+    return fail(ctx, PIFCM_E_INVALID,
+                "initial memberships must be finite, in [0, 1] and sum to 1 (+-1e-4) per voxel");
+  return PIFCM_OK;
+}
+
+SolveState init_state(const float* c0, int C, float lam, float xi, const pifcm_params* p,
+                      double* jhist) {
+  SolveState s;
+  std::memset(&s, 0, sizeof s);
+  for (int j = 0; j < C; ++j) s.c[0][j] = s.c[1][j] = c0[j];
+  s.lam = lam;
+  s.xi = xi;
+  s.eps = p->eps;
+  s.max_iter = p->max_iter;
+  s.iter = 0;
+  s.stop = p->max_iter == 0 ? 1 : 0;
+  s.counter = 0;
+  s.J_hist = jhist;
+  return s;
+}
+
+hipError_t launch_step(int C, const LaunchArgs& a, int grid, int ty, bool m2, bool fcm, bool step,
+                       hipStream_t s) {
+  return fcm ? launch_fcm(C, a, grid, m2, step, s) : launch_gather(C, a, grid, ty, m2, step, s);
+}
+
+LaunchArgs make_args(const VolDev* vols_dev, const PairDev* pairs_dev, const std::vector<VolDev>& vh,
+                     int nvol, int P, bool fcm, const pifcm_params* p) {
+  LaunchArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.vols = vols_dev;
+  a.pairs = pairs_dev;
+  a.nvol = nvol;
+  a.P = P;
+  a.q2_sqdist = (p->flags & PIFCM_Q2_SQDIST) ? 1 : 0;
+  a.m = p->m;
+  a.use_1d = fcm ? 1 : 0;
+  int acc = 0;
+  for (int b = 0; b < nvol; ++b) {
+    a.item_begin[b] = acc;
+    acc += P * (fcm ? vh[b].tiles1d : vh[b].tiles);
+  }
+  a.item_begin[nvol] = acc;
+  a.nitems = acc;
+  return a;
+}
+
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+pifcm_status pifcm_create(int device, void* hip_stream, pifcm_ctx** out) {
+  if (!out) return PIFCM_E_INVALID;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return PIFCM_E_INVALID;
+  }
+  pifcm_ctx* ctx = new pifcm_ctx();
+  ctx->device = device;
+  ctx->user = (hipStream_t)hip_stream;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipStreamCreateWithFlags(&ctx->s, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreate(&ctx->tm0) != hipSuccess || hipEventCreate(&ctx->tm1) != hipSuccess) {
+    (void)hipGetLastError();
+    pifcm_destroy(ctx);
+    return PIFCM_E_HIP;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
+  ensure(ctx, ctx->tvol, sizeof(VolDev) * kMaxBatchVols, "volume table");
+  ensure(ctx, ctx->tpair, sizeof(PairDev) * kMaxPairs, "pair table");
+  *out = ctx;
+  return PIFCM_OK;
+}
+
+void pifcm_destroy(pifcm_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->s) (void)hipStreamSynchronize(ctx->s);
+  if (ctx->graph.exec) (void)hipGraphExecDestroy(ctx->graph.exec);
+  if (ctx->graph.graph) (void)hipGraphDestroy(ctx->graph.graph);
+  for (DevBuf* b : {&ctx->invg, &ctx->ubuf, &ctx->partials, &ctx->states, &ctx->jhist, &ctx->tvol,
+                    &ctx->tpair, &ctx->flags})
+    if (b->p) (void)hipFree(b->p);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+  if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+  if (ctx->tm0) (void)hipEventDestroy(ctx->tm0);
+  if (ctx->tm1) (void)hipEventDestroy(ctx->tm1);
+  if (ctx->s) (void)hipStreamDestroy(ctx->s);
+  delete ctx;
+}
+
+pifcm_status pifcm_set_stream(pifcm_ctx* ctx, void* hip_stream) {
+  if (!ctx) return PIFCM_E_INVALID;
+  ctx->user = (hipStream_t)hip_stream;
+  ctx->err.clear();
+  return PIFCM_OK;
+}
+
+const char* pifcm_last_error(const pifcm_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+pifcm_status pifcm_set_timing(pifcm_ctx* ctx, int32_t enable) {
+  if (!ctx) return PIFCM_E_INVALID;
+  ctx->err.clear();
+  ctx->timing = enable != 0;
+  return PIFCM_OK;
+}
+
+pifcm_status pifcm_get_timing(pifcm_ctx* ctx, double* step_ms, int64_t* step_launches,
+                              int32_t reset) {
+  if (!ctx) return PIFCM_E_INVALID;
+  ctx->err.clear();
+  if (step_ms) *step_ms = ctx->step_ms;
+  if (step_launches) *step_launches = ctx->step_launches;
+  if (reset) {
+    ctx->step_ms = 0.0;
+    ctx->step_launches = 0;
+  }
+  return PIFCM_OK;
+}
+
+pifcm_status pifcm_normalize(pifcm_ctx* ctx, const float* raw, int64_t n, float* x_out) {
+  if (!ctx) return PIFCM_E_INVALID;
+  ctx->err.clear();
+  if (!raw || !x_out) return fail(ctx, PIFCM_E_INVALID, "raw and x_out must be non-NULL");
+  if (n < 1) return fail(ctx, PIFCM_E_INVALID, "n = %lld must be >= 1", (long long)n);
+  TRY(begin(ctx));
+  TRY(ensure(ctx, ctx->flags, 64, "flags"));
+  uint32_t* mm = (uint32_t*)ctx->flags.p + 4;
+  int* flag = (int*)ctx->flags.p;
+  const uint32_t init[2] = {0xffffffffu, 0u};
+  TRY(ensure_pinned(ctx, 4096));
+  std::memcpy(ctx->pinned, init, sizeof init);
+  HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), ctx->s));
+  HIPCHK(hipMemcpyAsync(mm, ctx->pinned, sizeof init, hipMemcpyHostToDevice, ctx->s));
+  // The flag is checked before x_out is written so an error leaves it alone.
+  HIPCHK(launch_minmax(raw, (size_t)n, mm, flag, ctx->s));
+  HIPCHK(hipMemcpyAsync((char*)ctx->pinned + 64, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->s));
+  HIPCHK(hipStreamSynchronize(ctx->s));
+  if (*(int*)((char*)ctx->pinned + 64))
+    return fail(ctx, PIFCM_E_NONFINITE, "the raw volume holds a NaN or Inf");
+  HIPCHK(launch_scale(raw, (size_t)n, mm, x_out, ctx->s));
+  TRY(finish(ctx));
+  return PIFCM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// One IFCM solve on the context's stream; shared by ifcm_solve and
+// pifcm_fcm_init.  U_final_out receives U^(T); host outputs optional.
+pifcm_status solve_impl(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
+                        float lambda, float xi, const float* centres_in, const float* U_in,
+                        float* U_out, float* centres_out, uint8_t* labels_out, double* J_out,
+                        int32_t* iters_out, double* J_hist_out) {
+  const int C = p->C;
+  const bool m2 = p->m == 2.0f;
+  const bool fcm = lambda == 0.0f && xi == 0.0f;
+  const size_t N = nvox(*vol);
+  std::vector<size_t> off;
+  const float* u0s[1] = {U_in};
+  TRY(prepare_volumes(ctx, vol, 1, C, u0s, off));
+  const TileShape ts = shape_for(ctx, C, m2, *vol);
+  std::vector<VolDev> vh{make_vol(*vol, (const float*)ctx->invg.p, ts)};
+  const int slots = std::max(vh[0].tiles, vh[0].tiles1d);
+  TRY(ensure(ctx, ctx->ubuf, N * C * sizeof(float), "memberships"));
+  TRY(ensure(ctx, ctx->partials, (size_t)slots * (2 * C + 1) * sizeof(float), "tile sums"));
+  TRY(ensure(ctx, ctx->states, sizeof(SolveState), "solve state"));
+  TRY(ensure(ctx, ctx->jhist, (size_t)std::max(1, p->max_iter) * sizeof(double), "objective history"));
+  TRY(ensure_pinned(ctx, sizeof(SolveState) + sizeof(PairDev) + sizeof(VolDev) +
+                             (size_t)std::max(1, p->max_iter) * sizeof(double) + 4096));
+  SolveState* st_dev = (SolveState*)ctx->states.p;
+  float* ubuf = (float*)ctx->ubuf.p;
+  PairDev pr{};
+  pr.U0 = U_in ? U_in : ubuf;
+  pr.Ua = U_out;
+  pr.Ub = ubuf;
+  pr.st = st_dev;
+  pr.partials = (float*)ctx->partials.p;
+
+  char* pin = (char*)ctx->pinned;
+  SolveState hs = init_state(centres_in, C, lambda, xi, p, (double*)ctx->jhist.p);
+  std::memcpy(pin, &hs, sizeof hs);
+  std::memcpy(pin + sizeof(SolveState), &pr, sizeof pr);
+  std::memcpy(pin + sizeof(SolveState) + sizeof(PairDev), &vh[0], sizeof(VolDev));
+  HIPCHK(hipMemcpyAsync(st_dev, pin, sizeof hs, hipMemcpyHostToDevice, ctx->s));
+  HIPCHK(hipMemcpyAsync(ctx->tpair.p, pin + sizeof(SolveState), sizeof pr, hipMemcpyHostToDevice, ctx->s));
+  HIPCHK(hipMemcpyAsync(ctx->tvol.p, pin + sizeof(SolveState) + sizeof(PairDev), sizeof(VolDev),
+                        hipMemcpyHostToDevice, ctx->s));
+  if (!U_in) HIPCHK(launch_init_u(C, vol->x, N, st_dev, p->m, m2, ubuf, ctx->s));
+
+  LaunchArgs a = make_args((const VolDev*)ctx->tvol.p, (const PairDev*)ctx->tpair.p, vh, 1, 1, fcm, p);
+  const int occ = fcm ? fcm_occupancy(C, m2, true) : gather_occupancy(C, ts.ty, m2, true);
+  const int grid = grid_for(ctx, a.nitems, occ);
+  int t = 0;
+  SolveState* hst = (SolveState*)pin;
+  TRY(timing_begin(ctx));
+  while (t < p->max_iter) {
+    const int k = p->eps > 0.f ? std::min(kChunk, p->max_iter - t) : p->max_iter - t;
+    for (int i = 0; i < k; ++i) HIPCHK(launch_step(C, a, grid, ts.ty, m2, fcm, true, ctx->s));
+    t += k;
+    if (p->eps > 0.f && t < p->max_iter) {
+      HIPCHK(hipMemcpyAsync(hst, st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, ctx->s));
+      HIPCHK(hipStreamSynchronize(ctx->s));
+      if (hst->stop) break;
+    }
+  }
+  TRY(timing_end(ctx));
+  // Objective of the final state (the fitness).
+  LaunchArgs ae = a;
+  const int occe = fcm ? fcm_occupancy(C, m2, false) : gather_occupancy(C, ts.ty, m2, false);
+  HIPCHK(launch_step(C, ae, grid_for(ctx, a.nitems, occe), ts.ty, m2, fcm, false, ctx->s));
+  HIPCHK(hipMemcpyAsync(hst, st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, ctx->s));
+  HIPCHK(hipStreamSynchronize(ctx->s));
+  const int T = hst->iter;
+  TRY(timing_collect(ctx, t));
+  const float* Ufin = u_state_of(pr, T);
+  if (labels_out) HIPCHK(launch_labels(Ufin, N, C, labels_out, ctx->s));
+  if (Ufin != U_out) HIPCHK(hipMemcpyAsync(U_out, Ufin, N * C * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+  double* jh = (double*)(pin + sizeof(SolveState) + 1024);
+  if (J_hist_out && T > 0)
+    HIPCHK(hipMemcpyAsync(jh, ctx->jhist.p, (size_t)T * sizeof(double), hipMemcpyDeviceToHost, ctx->s));
+  HIPCHK(hipStreamSynchronize(ctx->s));
+  if (centres_out)
+    for (int j = 0; j < C; ++j) centres_out[j] = hst->c[T & 1][j];
+  if (J_out) *J_out = hst->J_eval;
+  if (iters_out) *iters_out = T;
+  if (J_hist_out && T > 0) std::memcpy(J_hist_out, jh, (size_t)T * sizeof(double));
+  return PIFCM_OK;
+}
+
+pifcm_status check_solve_args(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
+                              float lambda, float xi, const float* centres_in, const float* U_in,
+                              const float* U_out) {
+  TRY(check_volume(ctx, vol));
+  TRY(check_params(ctx, p));
+  if (!std::isfinite(lambda) || !std::isfinite(xi))
+    return fail(ctx, PIFCM_E_INVALID, "lambda and xi must be finite");
+  if (!centres_in) return fail(ctx, PIFCM_E_INVALID, "centres_in is NULL");
+  for (int j = 0; j < p->C; ++j)
+    if (!std::isfinite(centres_in[j])) return fail(ctx, PIFCM_E_INVALID, "centres_in[%d] is not finite", j);
+  if (!U_out) return fail(ctx, PIFCM_E_INVALID, "U_out is NULL");
+  if (!aligned16(U_out) || (U_in && !aligned16(U_in)))
+    return fail(ctx, PIFCM_E_INVALID, "membership buffers must be 16-byte aligned");
+  const size_t bytes = nvox(*vol) * p->C * sizeof(float);
+  if (U_in && ranges_overlap(U_in, bytes, U_out, bytes))
+    return fail(ctx, PIFCM_E_INVALID, "U_out must not overlap U_in");
+  return PIFCM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pifcm_status ifcm_solve(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
+                        float lambda, float xi, const float* centres_in, const float* U_in,
+                        float* U_out, float* centres_out, uint8_t* labels_out, double* J_out,
+                        int32_t* iters_out, double* J_hist_out) {
+  if (!ctx) return PIFCM_E_INVALID;
+  ctx->err.clear();
+  TRY(check_solve_args(ctx, vol, p, lambda, xi, centres_in, U_in, U_out));
+  TRY(begin(ctx));
+  float c_tmp[kMaxC];
+  double J = 0.0;
+  int32_t T = 0;
+  std::vector<double> jh((size_t)std::max(1, p->max_iter));
+  TRY(solve_impl(ctx, vol, p, lambda, xi, centres_in, U_in, U_out, c_tmp, labels_out, &J, &T,
+                 J_hist_out ? jh.data() : nullptr));
+  TRY(finish(ctx));
+  if (centres_out) std::memcpy(centres_out, c_tmp, sizeof(float) * p->C);
+  if (J_out) *J_out = J;
+  if (iters_out) *iters_out = T;
+  if (J_hist_out) std::memcpy(J_hist_out, jh.data(), sizeof(double) * (size_t)T);
+  return PIFCM_OK;
+}
+
+pifcm_status pifcm_fcm_init(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
+                            float* U0_out, float* centres_out, int32_t* iters_out) {
+  if (!ctx) return PIFCM_E_INVALID;
+  ctx->err.clear();
+  if (!p) return fail(ctx, PIFCM_E_INVALID, "params is NULL");
+  float c0[kMaxC];
+  const int C = std::max(2, std::min(p->C, kMaxC));
+  for (int j = 0; j < C; ++j) c0[j] = (float)(((double)j + 0.5) / (double)p->C);
+  TRY(check_solve_args(ctx, vol, p, 0.f, 0.f, c0, nullptr, U0_out));
+  if (!centres_out) return fail(ctx, PIFCM_E_INVALID, "centres_out is NULL");
+  TRY(begin(ctx));
+  float c1[kMaxC];
+  int32_t T = 0;
+  TRY(solve_impl(ctx, vol, p, 0.f, 0.f, c0, nullptr, U0_out, c1, nullptr, nullptr, &T, nullptr));
+  int32_t perm[kMaxC];
+  for (int j = 0; j < C; ++j) perm[j] = j;
+  std::stable_sort(perm, perm + C, [&](int a, int b) { return c1[a] < c1[b]; });
+  HIPCHK(launch_permute(U0_out, nvox(*vol), C, perm, U0_out, ctx->s));
+  HIPCHK(hipStreamSynchronize(ctx->s));
+  TRY(finish(ctx));
+  for (int j = 0; j < C; ++j) centres_out[j] = c1[perm[j]];
+  if (iters_out) *iters_out = T;
+  return PIFCM_OK;
+}
+
+pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
+                            const pifcm_params* p, const float* particles, int32_t P,
+                            const float* centres0, const float* const* U0, double* fitness_out,
+                            float* centres_out, int32_t* iters_out, int32_t mode) {
+  if (!ctx) return PIFCM_E_INVALID;
+  ctx->err.clear();
+  if (!vols || B < 1 || B > kMaxBatchVols)
+    return fail(ctx, PIFCM_E_INVALID, "B = %d outside [1, %d]", B, kMaxBatchVols);
+  if (P < 1 || (long)B * P > kMaxPairs)
+    return fail(ctx, PIFCM_E_INVALID, "P = %d: need 1 <= P and B * P <= %d", P, kMaxPairs);
+  if (mode != PIFCM_SWARM_BATCHED && mode != PIFCM_SWARM_PLAIN)
+    return fail(ctx, PIFCM_E_INVALID, "unknown mode %d", mode);
+  TRY(check_params(ctx, p));
+  if (!particles || !centres0 || !U0 || !fitness_out)
+    return fail(ctx, PIFCM_E_INVALID, "particles, centres0, U0 and fitness_out must be non-NULL");
+  const int C = p->C;
+  const bool m2 = p->m == 2.0f;
+  for (int b = 0; b < B; ++b) {
+    TRY(check_volume(ctx, &vols[b]));
+    if (!U0[b] || !aligned16(U0[b])) return fail(ctx, PIFCM_E_INVALID, "U0[%d] is NULL or not 16-byte aligned", b);
+    for (int j = 0; j < C; ++j)
+      if (!std::isfinite(centres0[b * C + j])) return fail(ctx, PIFCM_E_INVALID, "centres0[%d][%d] is not finite", b, j);
+  }
+  for (long k = 0; k < 2L * B * P; ++k)
+    if (!std::isfinite(particles[k])) return fail(ctx, PIFCM_E_INVALID, "particle value %ld is not finite", k);
+  TRY(begin(ctx));
+  std::vector<size_t> off;
+  TRY(prepare_volumes(ctx, vols, B, C, U0, off));
+
+  // Tile shape: one per launch (the batched kernel has one TY).
+  const TileShape ts0 = shape_for(ctx, C, m2, vols[0]);
+  std::vector<VolDev> vh(B);
+  size_t ubytes = 0, slots = 0;
+  std::vector<size_t> uoff(B), soff(B);
+  for (int b = 0; b < B; ++b) {
+    TileShape ts = shape_for(ctx, C, m2, vols[b]);
+    ts.ty = ts0.ty;
+    vh[b] = make_vol(vols[b], (const float*)ctx->invg.p + off[b], ts);
+    uoff[b] = ubytes;
+    ubytes += (size_t)P * 2 * ((nvox(vols[b]) * C + 63) / 64 * 64) * sizeof(float);
+    soff[b] = slots;
+    slots += (size_t)P * std::max(vh[b].tiles, vh[b].tiles1d);
+  }
+  const size_t npairs = (size_t)B * P;
+  TRY(ensure(ctx, ctx->ubuf, ubytes, "swarm memberships"));
+  TRY(ensure(ctx, ctx->partials, slots * (2 * C + 1) * sizeof(float), "tile sums"));
+  TRY(ensure(ctx, ctx->states, npairs * sizeof(SolveState), "solve states"));
+  const size_t pin_bytes = npairs * (sizeof(SolveState) + sizeof(PairDev)) + sizeof(VolDev) * B + 4096;
+  TRY(ensure_pinned(ctx, pin_bytes));
+  for (int b = 0; b < B; ++b) vh[b].invg = (const float*)ctx->invg.p + off[b];
+
+  char* pin = (char*)ctx->pinned;
+  SolveState* hs = (SolveState*)pin;
+  PairDev* hp = (PairDev*)(pin + npairs * sizeof(SolveState));
+  VolDev* hv = (VolDev*)(pin + npairs * (sizeof(SolveState) + sizeof(PairDev)));
+  SolveState* st_dev = (SolveState*)ctx->states.p;
+  for (int b = 0; b < B; ++b) {
+    hv[b] = vh[b];
+    const size_t Nb = nvox(vols[b]);
+    const size_t ustride = (Nb * C + 63) / 64 * 64;
+    const int tb = std::max(vh[b].tiles, vh[b].tiles1d);
+    for (int q = 0; q < P; ++q) {
+      const size_t k = (size_t)b * P + q;
+      hs[k] = init_state(centres0 + (size_t)b * C, C, particles[2 * k], particles[2 * k + 1], p, nullptr);
+      PairDev& pr = hp[k];
+      pr.U0 = U0[b];
+      pr.Ua = (float*)((char*)ctx->ubuf.p + uoff[b]) + (size_t)q * 2 * ustride;
+      pr.Ub = pr.Ua + ustride;
+      pr.st = st_dev + k;
+      pr.partials = (float*)ctx->partials.p + (soff[b] + (size_t)q * tb) * (2 * C + 1);
+    }
+  }
+  HIPCHK(hipMemcpyAsync(st_dev, hs, npairs * sizeof(SolveState), hipMemcpyHostToDevice, ctx->s));
+  HIPCHK(hipMemcpyAsync(ctx->tpair.p, hp, npairs * sizeof(PairDev), hipMemcpyHostToDevice, ctx->s));
+  HIPCHK(hipMemcpyAsync(ctx->tvol.p, hv, B * sizeof(VolDev), hipMemcpyHostToDevice, ctx->s));
+
+  // lambda = xi = 0 for every particle: plain FCM kernels.
+  bool fcm = true;
+  for (long k = 0; k < 2L * B * P; ++k) fcm = fcm && particles[k] == 0.0f;
+  const VolDev* vdev = (const VolDev*)ctx->tvol.p;
+  const PairDev* pdev = (const PairDev*)ctx->tpair.p;
+  const int occ = fcm ? fcm_occupancy(C, m2, true) : gather_occupancy(C, ts0.ty, m2, true);
+  const int occe = fcm ? fcm_occupancy(C, m2, false) : gather_occupancy(C, ts0.ty, m2, false);
+
+  int64_t launches = 0;
+  auto all_stopped = [&](bool& done) -> pifcm_status {
+    HIPCHK(hipMemcpyAsync(hs, st_dev, npairs * sizeof(SolveState), hipMemcpyDeviceToHost, ctx->s));
+    HIPCHK(hipStreamSynchronize(ctx->s));
+    done = true;
+    for (size_t k = 0; k < npairs; ++k) done = done && hs[k].stop;
+    return PIFCM_OK;
+  };
+
+  if (mode == PIFCM_SWARM_BATCHED) {
+    LaunchArgs a = make_args(vdev, pdev, vh, B, P, fcm, p);
+    const int grid = grid_for(ctx, a.nitems, occ);
+    const int chunk = p->eps > 0.f ? std::min(kChunk, std::max(1, p->max_iter)) : std::max(1, p->max_iter);
+    // Capture `chunk` fused launches once; replay until every pair stops.
+    std::vector<char> key(sizeof(LaunchArgs) + 5 * sizeof(int));
+    std::memcpy(key.data(), &a, sizeof a);
+    const int extra[5] = {grid, ts0.ty, C * 2 + (int)m2, (int)fcm, chunk};
+    std::memcpy(key.data() + sizeof a, extra, sizeof extra);
+    if (ctx->graph.key != key || !ctx->graph.exec) {
+      if (ctx->graph.exec) HIPCHK(hipGraphExecDestroy(ctx->graph.exec));
+      if (ctx->graph.graph) HIPCHK(hipGraphDestroy(ctx->graph.graph));
+      ctx->graph.exec = nullptr;
+      ctx->graph.graph = nullptr;
+      ctx->graph.key.clear();
+      HIPCHK(hipStreamBeginCapture(ctx->s, hipStreamCaptureModeThreadLocal));
+      for (int i = 0; i < chunk; ++i) {
+        hipError_t e = launch_step(C, a, grid, ts0.ty, m2, fcm, true, ctx->s);
+        if (e != hipSuccess) {
+          hipGraph_t g = nullptr;
+          (void)hipStreamEndCapture(ctx->s, &g);
+          if (g) (void)hipGraphDestroy(g);
+          return fail(ctx, PIFCM_E_HIP, "capture of the swarm step failed: %s", hipGetErrorString(e));
+        }
+      }
+      HIPCHK(hipStreamEndCapture(ctx->s, &ctx->graph.graph));
+      HIPCHK(hipGraphInstantiate(&ctx->graph.exec, ctx->graph.graph, nullptr, nullptr, 0));
+      ctx->graph.key = key;
+    }
+    int t = 0;
+    TRY(timing_begin(ctx));
+    while (t < p->max_iter) {
+      HIPCHK(hipGraphLaunch(ctx->graph.exec, ctx->s));
+      t += chunk;
+      if (t < p->max_iter) {
+        bool done = false;
+        TRY(all_stopped(done));
+        if (done) break;
+      }
+    }
+    TRY(timing_end(ctx));
+    launches = t;
+    HIPCHK(launch_step(C, a, grid_for(ctx, a.nitems, occe), ts0.ty, m2, fcm, false, ctx->s));
+  } else {
+    // One launch per (volume, particle) per iteration.
+    std::vector<LaunchArgs> args(npairs);
+    std::vector<int> grids(npairs), gride(npairs);
+    for (int b = 0; b < B; ++b) {
+      std::vector<VolDev> one{vh[b]};
+      for (int q = 0; q < P; ++q) {
+        const size_t k = (size_t)b * P + q;
+        args[k] = make_args(vdev + b, pdev + k, one, 1, 1, fcm, p);
+        grids[k] = grid_for(ctx, args[k].nitems, occ);
+        gride[k] = grid_for(ctx, args[k].nitems, occe);
+      }
+    }
+    int t = 0;
+    TRY(timing_begin(ctx));
+    while (t < p->max_iter) {
+      const int k = p->eps > 0.f ? std::min(kChunk, p->max_iter - t) : p->max_iter - t;
+      for (int i = 0; i < k; ++i)
+        for (size_t q = 0; q < npairs; ++q)
+          HIPCHK(launch_step(C, args[q], grids[q], ts0.ty, m2, fcm, true, ctx->s));
+      t += k;
+      if (t < p->max_iter) {
+        bool done = false;
+        TRY(all_stopped(done));
+        if (done) break;
+      }
+    }
+    TRY(timing_end(ctx));
+    launches = (int64_t)t * (int64_t)npairs;
+    for (size_t q = 0; q < npairs; ++q)
+      HIPCHK(launch_step(C, args[q], gride[q], ts0.ty, m2, fcm, false, ctx->s));
+  }
+  HIPCHK(hipMemcpyAsync(hs, st_dev, npairs * sizeof(SolveState), hipMemcpyDeviceToHost, ctx->s));
+  HIPCHK(hipStreamSynchronize(ctx->s));
+  TRY(timing_collect(ctx, launches));
+  TRY(finish(ctx));
+  for (size_t k = 0; k < npairs; ++k) {
+    const int T = hs[k].iter;
+    fitness_out[k] = hs[k].J_eval;
+    if (centres_out)
+      for (int j = 0; j < C; ++j) centres_out[k * C + j] = hs[k].c[T & 1][j];
+    if (iters_out) iters_out[k] = T;
+  }
+  return PIFCM_OK;
+}
+
+pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
+                           float lambda, float xi, const float* centres0, const float* U0,
+                           int32_t K, int32_t ckpt_every, double* J_out, double* dJ_dlambda,
+                           double* dJ_dxi, double* dJ_dcentres) {
+  if (!ctx) return PIFCM_E_INVALID;
+  ctx->err.clear();
+  (void)vol; (void)p; (void)lambda; (void)xi; (void)centres0; (void)U0; (void)K;
+  (void)ckpt_every; (void)J_out; (void)dJ_dlambda; (void)dJ_dxi; (void)dJ_dcentres;
+  return fail(ctx, PIFCM_E_UNSUPPORTED, "ifcm_backward is not built yet");
+}
+
+pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, const pifcm_params* p,
+                        int32_t P, char* best_out, int32_t best_len) {
+  if (!ctx) return PIFCM_E_INVALID;
+  ctx->err.clear();
+  (void)vols; (void)B; (void)p; (void)P; (void)best_out; (void)best_len;
+  return fail(ctx, PIFCM_E_UNSUPPORTED, "pifcm_tune is not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,32 @@
+// pifcm_kernels.h -- launchers of the HIP kernels (internal to libpifcm).
+#pragma once
+#include <algorithm>
+#include <type_traits>
+
+#include "pifcm_device.h"
+
+namespace pifcm {
+
+// Fused IFCM step (step = true) or objective-only pass (step = false) over
+// the tiles of a launch; ty = rows per tile (2, 4 or 8).
+hipError_t launch_gather(int C, const LaunchArgs& a, int grid, int ty, bool m2, bool step,
+                         hipStream_t s);
+// Pointwise FCM step / objective (lambda = xi = 0).
+hipError_t launch_fcm(int C, const LaunchArgs& a, int grid, bool m2, bool step, hipStream_t s);
+hipError_t launch_init_u(int C, const float* x, size_t N, const SolveState* st, float m, bool m2,
+                         float* U, hipStream_t s);
+hipError_t launch_invariants(const float* x, float* invg, int nx, int ny, int nz, int* flag,
+                             hipStream_t s);
+hipError_t launch_check_rows(const float* U, size_t N, int C, int* flag, hipStream_t s);
+hipError_t launch_labels(const float* U, size_t N, int C, uint8_t* out, hipStream_t s);
+hipError_t launch_permute(const float* U, size_t N, int C, const int32_t* perm, float* out,
+                          hipStream_t s);
+// Min-max normalisation: exact min/max keys into mm[0..1] (mm preset to
+// {0xffffffff, 0}) and a non-finite flag, then the scaling pass.
+hipError_t launch_minmax(const float* raw, size_t n, uint32_t* mm, int* flag, hipStream_t s);
+hipError_t launch_scale(const float* raw, size_t n, const uint32_t* mm, float* out, hipStream_t s);
+// Resident work groups per CU of the gather / pointwise kernels.
+int gather_occupancy(int C, int ty, bool m2, bool step);
+int fcm_occupancy(int C, bool m2, bool step);
+
+}  // namespace pifcm

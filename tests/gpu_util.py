@@ -1,0 +1,64 @@
+"""Helpers of the GPU parity tests (comparison rules, device copies)."""
+import numpy as np
+
+# Parity bar: memberships and centres within 1e-4 relative, measured
+# norm-wise (max |gpu - oracle| / max |oracle| per array) because the
+# element-wise relative error of a membership near 0 carries no meaning.
+TOL = 1e-4
+# Labels must match except where the oracle's two largest memberships are
+# closer than this (both precisions may then pick either cluster).
+TIE_BAND = 1e-5
+
+
+# For lambda + xi > 1 the attraction factor 1 - lambda H - xi F of eq (4)
+# changes sign on a data-dependent set of voxels and the 1e-12 floor of the
+# squared distance engages there; the membership map is ill-conditioned at
+# those voxels (a plain float32 emulation of the step in numpy differs from
+# float64 by up to 2e-3 max-norm after a few iterations while the 2-norm
+# stays below 4e-5).  In that saturated regime memberships are held to the
+# 2-norm relative error and labels to a wider tie band; centres and J keep
+# the max-norm bar.
+SATURATED_TIE_BAND = 1e-2
+
+
+def saturated(lam, xi):
+    return lam + xi > 1.0
+
+
+def rel2(a, ref):
+    a = np.asarray(a, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return float(np.linalg.norm((a - ref).ravel()) / max(np.linalg.norm(ref.ravel()), 1e-300))
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, ref):
+    a = np.asarray(a, np.float64)
+    ref = np.asarray(ref, np.float64)
+    scale = float(np.max(np.abs(ref))) if ref.size else 1.0
+    return float(np.max(np.abs(a - ref))) / max(scale, 1e-300)
+
+
+def check_labels(lab_gpu, U_ref, C, band=TIE_BAND):
+    U = np.asarray(U_ref, np.float64).reshape(-1, C)
+    srt = np.sort(U, axis=1)
+    gap = srt[:, -1] - srt[:, -2]
+    ref = np.argmax(U, axis=1)
+    ok = gap >= band
+    lab = np.asarray(lab_gpu).reshape(-1)
+    bad = np.nonzero(lab[ok] != ref[ok])[0]
+    assert bad.size == 0, f"{bad.size} labels differ outside the tie band"
+    return int((~ok).sum())
+
+
+def random_memberships_f32(rng, n, C):
+    a = rng.random((n, C)) + 0.05
+    return (a / a.sum(1, keepdims=True)).astype(np.float32)

@@ -1,0 +1,288 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Every comparison runs both sides on the same seeded inputs: the raw phantoms
+of `synth` are normalised by each side separately (and checked bit-equal),
+initial memberships are drawn in float32 and handed to both.  The bar is
+1e-4 relative (norm-wise) on memberships and centres, labels bit-exact
+outside the 1e-5 tie band, integers (iteration counts) exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import (SATURATED_TIE_BAND, TIE_BAND, TOL, check_labels, dev, host,
+                      random_memberships_f32, rel, rel2, saturated)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "the GPU tests need a GPU"
+    from paper_2002_01981_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _P(**kw):
+    from paper_2002_01981_amd import Params
+    return Params(**kw)
+
+
+def _both_normalised(ctx, raw):
+    xo = oracle.normalize(raw)
+    xg = ctx.pifcm_normalize(dev(raw))
+    assert np.array_equal(host(xg), xo), "normalisation differs"
+    return xo, xg
+
+
+def _run_steps(ctx, raw, C, lam, xi, steps, m=2.0, flags=0, seed=0, c0=None):
+    rng = np.random.default_rng(seed)
+    xo, xg = _both_normalised(ctx, raw)
+    U0 = random_memberships_f32(rng, xo.size, C)
+    if c0 is None:
+        c0 = np.linspace(0.1, 0.9, C).astype(np.float32)
+    p = _P(C=C, m=m, eps=0.0, max_iter=steps, flags=flags)
+    g = ctx.ifcm_solve(xg, p, lam, xi, c0, U_in=dev(U0), labels=True, want_hist=True)
+    po = oracle.Params(C=C, m=m, eps=0.0, max_iter=steps, flags=flags)
+    o = oracle.solve(xo, c0.astype(np.float64), po, lam, xi, U0=U0.astype(np.float64),
+                     want_hist=True)
+    return g, o
+
+
+def _assert_close(g, o, C, lam, xi, tol=TOL):
+    assert g["iters"] == o["iters"]
+    sat = saturated(lam, xi)
+    eu = (rel2 if sat else rel)(host(g["U"]), o["U"])
+    ec = rel(g["c"], o["c"])
+    ej = abs(g["J"] - o["J"]) / abs(o["J"])
+    assert eu <= tol, f"memberships off by {eu:.3g}"
+    assert ec <= tol, f"centres off by {ec:.3g}"
+    assert ej <= tol, f"objective off by {ej:.3g}"
+    if "J_hist" in g and len(o.get("J_hist", [])):
+        eh = np.max(np.abs(g["J_hist"] - o["J_hist"]) / np.abs(o["J_hist"]))
+        assert eh <= tol, f"objective history off by {eh:.3g}"
+    check_labels(host(g["labels"]), o["U"], C, SATURATED_TIE_BAND if sat else TIE_BAND)
+    return eu, ec, ej
+
+
+# ------------------------------------------------------------ normalisation
+def test_normalize_bit_exact(ctx):
+    for raw in (synth.nested_ellipsoids()[0],
+                synth.random_ellipsoids(shape=(6, 70, 90), seed=9)[0],
+                synth.brain_shells(shape=(20, 31, 27), seed=4)[0]):
+        _both_normalised(ctx, raw)
+
+
+def test_normalize_in_place_and_constant(ctx):
+    raw = synth.random_ellipsoids(shape=(4, 33, 65), seed=3)[0]
+    t = dev(raw)
+    ctx.pifcm_normalize(t, out=t)
+    assert np.array_equal(host(t), oracle.normalize(raw))
+    c = np.full((3, 4, 5), 2.5, np.float32)
+    assert np.all(host(ctx.pifcm_normalize(dev(c))) == 0)
+
+
+# ------------------------------------------------------------- step parity
+@pytest.mark.parametrize("shape", [(70, 10, 150), (33, 9, 64), (5, 7, 65), (40, 3, 129),
+                                   (2, 70, 20)])
+@pytest.mark.parametrize("lam,xi", [(0.3, 0.4), (0.0, 0.0), (0.9, 0.7)])
+def test_steps_span_tiles(ctx, shape, lam, xi):
+    """Tiles are 64 x 4 columns by up to 32 planes: these shapes cover several
+    tiles in every direction with ragged tails."""
+    raw = synth.random_ellipsoids(shape=shape, seed=sum(shape), sigma=0.07)[0]
+    g, o = _run_steps(ctx, raw, 4, lam, xi, steps=3, seed=shape[0])
+    _assert_close(g, o, 4, lam, xi)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 2), (2, 1, 1), (1, 3, 2), (3, 1, 64),
+                                   (1, 1, 65), (2, 5, 129), (4, 4, 2)])
+def test_tiny_and_degenerate_volumes(ctx, shape):
+    rng = np.random.default_rng(sum(shape) + 7)
+    raw = rng.random(shape).astype(np.float32)
+    g, o = _run_steps(ctx, raw, 3, 0.5, 0.3, steps=4, seed=3)
+    _assert_close(g, o, 3, 0.5, 0.3)
+
+
+@pytest.mark.parametrize("C", [2, 3, 5, 8, 16])
+def test_cluster_counts(ctx, C):
+    raw = synth.random_ellipsoids(shape=(9, 11, 70), seed=C, sigma=0.07)[0]
+    g, o = _run_steps(ctx, raw, C, 0.4, 0.3, steps=3, seed=C)
+    _assert_close(g, o, C, 0.4, 0.3)
+
+
+@pytest.mark.parametrize("m", [2.5, 1.5])
+def test_general_fuzziness(ctx, m):
+    raw = synth.random_ellipsoids(shape=(7, 9, 80), seed=11, sigma=0.07)[0]
+    g, o = _run_steps(ctx, raw, 4, 0.35, 0.25, steps=3, m=m, seed=5)
+    _assert_close(g, o, 4, 0.35, 0.25)
+
+
+def test_q2_reading_flag(ctx):
+    from paper_2002_01981_amd import PIFCM_Q2_SQDIST
+    raw = synth.random_ellipsoids(shape=(6, 10, 70), seed=21, sigma=0.07)[0]
+    g, o = _run_steps(ctx, raw, 4, 0.3, 0.6, steps=3, flags=PIFCM_Q2_SQDIST, seed=2)
+    _assert_close(g, o, 4, 0.3, 0.6)
+
+
+def test_flat_neighbourhoods(ctx):
+    """Voxels whose neighbours all share their intensity take the mean
+    branch of eq (5)."""
+    raw = np.zeros((6, 8, 70), np.float32)
+    raw[:, :, 35:] = 1.0
+    raw[2:4, 3:5, 10:12] = 0.5
+    g, o = _run_steps(ctx, raw, 3, 0.5, 0.4, steps=4, seed=9)
+    _assert_close(g, o, 3, 0.5, 0.4)
+
+
+def test_attraction_beyond_one_clamps(ctx):
+    """lambda + xi > 1 drives the factor of eq (4) to <= 0: both sides floor
+    the squared distance at 1e-12."""
+    raw = synth.random_ellipsoids(shape=(8, 12, 70), seed=31, sigma=0.07)[0]
+    g, o = _run_steps(ctx, raw, 4, 1.0, 1.0, steps=4, seed=4)
+    _assert_close(g, o, 4, 1.0, 1.0)
+
+
+# -------------------------------------------------------- solves end to end
+def test_fcm_init_parity(ctx):
+    raw, _ = synth.nested_ellipsoids()
+    xo, xg = _both_normalised(ctx, raw)
+    p = _P(C=4, m=2.0, eps=1e-5, max_iter=50)
+    cg, Ug, itg = ctx.pifcm_fcm_init(xg, p)
+    co, Uo, ito = oracle.fcm_init(xo, oracle.Params(C=4, m=2.0, eps=1e-5, max_iter=50))
+    assert itg == ito
+    assert rel(cg, co) <= TOL
+    assert rel(host(Ug), Uo) <= TOL
+    assert np.all(np.diff(cg) >= 0)
+
+
+@pytest.mark.parametrize("lam,xi", [(0.25, 0.5), (0.6, 0.3), (0.05, 0.9)])
+def test_solve_nested32_end_to_end(ctx, lam, xi):
+    """The CPU-sized workload: each side computes its own FCM initial state
+    and then the IFCM solve with the convergence rule."""
+    raw, _ = synth.nested_ellipsoids()
+    xo, xg = _both_normalised(ctx, raw)
+    p = _P(C=4, m=2.0, eps=1e-5, max_iter=50)
+    po = oracle.Params(C=4, m=2.0, eps=1e-5, max_iter=50)
+    cg, Ug, _ = ctx.pifcm_fcm_init(xg, p)
+    co, Uo, _ = oracle.fcm_init(xo, po)
+    g = ctx.ifcm_solve(xg, p, lam, xi, cg, U_in=Ug, labels=True, want_hist=True)
+    o = oracle.solve(xo, co, po, lam, xi, U0=Uo, want_hist=True)
+    _assert_close(g, o, 4, lam, xi)
+
+
+def test_determinism(ctx):
+    raw = synth.random_ellipsoids(shape=(20, 30, 100), seed=5)[0]
+    xg = ctx.pifcm_normalize(dev(raw))
+    p = _P(C=4, m=2.0, eps=0.0, max_iter=6)
+    c0 = np.array([0.1, 0.4, 0.6, 0.9], np.float32)
+    a = ctx.ifcm_solve(xg, p, 0.3, 0.3, c0, labels=True)
+    b = ctx.ifcm_solve(xg, p, 0.3, 0.3, c0, labels=True)
+    assert np.array_equal(host(a["U"]), host(b["U"]))
+    assert np.array_equal(a["c"], b["c"]) and a["J"] == b["J"]
+    assert np.array_equal(host(a["labels"]), host(b["labels"]))
+
+
+def test_constant_volume(ctx):
+    raw = np.full((5, 6, 70), 3.0, np.float32)
+    xg = ctx.pifcm_normalize(dev(raw))
+    p = _P(C=4, m=2.0, eps=0.0, max_iter=5)
+    c, U0, _ = ctx.pifcm_fcm_init(xg, p)
+    assert np.all(c == 0)
+    g = ctx.ifcm_solve(xg, p, 0.6, 0.3, c, U_in=U0, labels=True)
+    np.testing.assert_allclose(host(g["U"]), 0.25, atol=1e-6)
+    assert np.all(g["c"] == 0)
+    assert np.all(host(g["labels"]) == 0)
+
+
+# ------------------------------------------------------------------ swarm
+def _swarm_case(ctx, shapes, P, eps, max_iter, seed):
+    raws = [synth.random_ellipsoids(shape=s, seed=seed + b, sigma=0.07)[0]
+            for b, s in enumerate(shapes)]
+    p = _P(C=4, m=2.0, eps=eps, max_iter=max_iter)
+    po = oracle.Params(C=4, m=2.0, eps=eps, max_iter=max_iter)
+    xs, inits = [], []
+    for raw in raws:
+        xo, xg = _both_normalised(ctx, raw)
+        xs.append((xo, xg))
+        cg, Ug, _ = ctx.pifcm_fcm_init(xg, _P(C=4, m=2.0, eps=0.0, max_iter=10))
+        inits.append((cg, Ug))
+    parts = synth.uniform_particles(seed, P)
+    return raws, p, po, xs, inits, parts
+
+
+def test_swarm_batched_equals_plain_and_oracle(ctx):
+    from paper_2002_01981_amd import PIFCM_SWARM_BATCHED, PIFCM_SWARM_PLAIN
+    shapes = [(10, 20, 70), (7, 33, 40), (12, 9, 130)]
+    raws, p, po, xs, inits, parts = _swarm_case(ctx, shapes, P=5, eps=1e-5, max_iter=15, seed=40)
+    c0 = np.stack([c for c, _ in inits])
+    U0 = [u for _, u in inits]
+    xg = [x for _, x in xs]
+    bat = ctx.swarm_evaluate(xg, p, parts, c0, U0, mode=PIFCM_SWARM_BATCHED)
+    pla = ctx.swarm_evaluate(xg, p, parts, c0, U0, mode=PIFCM_SWARM_PLAIN)
+    assert np.array_equal(bat["fitness"], pla["fitness"])
+    assert np.array_equal(bat["centres"], pla["centres"])
+    assert np.array_equal(bat["iters"], pla["iters"])
+    again = ctx.swarm_evaluate(xg, p, parts, c0, U0, mode=PIFCM_SWARM_BATCHED)
+    assert np.array_equal(bat["fitness"], again["fitness"])
+    for b, (xo, _) in enumerate(xs):
+        U0o = host(U0[b]).astype(np.float64)
+        for q in range(parts.shape[0]):
+            lam, xi = parts[q]
+            o = oracle.solve(xo, c0[b].astype(np.float64), po, float(lam), float(xi), U0=U0o)
+            assert bat["iters"][b, q] == o["iters"]
+            assert abs(bat["fitness"][b, q] - o["J"]) <= TOL * abs(o["J"])
+            assert rel(bat["centres"][b, q], o["c"]) <= TOL
+
+
+def test_swarm_matches_solve(ctx):
+    """A pair of the batched launch and a lone solve with the same tile
+    shapes run the same arithmetic in the same order: bit-identical."""
+    shapes = [(9, 17, 66), (5, 40, 33)]
+    raws, p, po, xs, inits, parts = _swarm_case(ctx, shapes, P=3, eps=0.0, max_iter=5, seed=60)
+    c0 = np.stack([c for c, _ in inits])
+    U0 = [u for _, u in inits]
+    xg = [x for _, x in xs]
+    bat = ctx.swarm_evaluate(xg, p, parts, c0, U0)
+    for b in range(len(shapes)):
+        for q in range(3):
+            s = ctx.ifcm_solve(xg[b], p, float(parts[q, 0]), float(parts[q, 1]), c0[b], U_in=U0[b])
+            assert s["J"] == bat["fitness"][b, q]
+            assert np.array_equal(s["c"], bat["centres"][b, q])
+
+
+# ---------------------------------------------------------------- errors
+def test_error_paths(ctx):
+    import torch
+    from paper_2002_01981_amd import PifcmError
+    from paper_2002_01981_amd.abi import (PIFCM_E_INVALID, PIFCM_E_NONFINITE,
+                                          PIFCM_E_UNSUPPORTED)
+    x = ctx.pifcm_normalize(dev(synth.random_ellipsoids(shape=(4, 6, 70), seed=1)[0]))
+    c0 = np.array([0.1, 0.4, 0.6, 0.9], np.float32)
+
+    def status(fn):
+        with pytest.raises(PifcmError) as e:
+            fn()
+        return e.value.status
+
+    assert status(lambda: ctx.ifcm_solve(x, _P(C=1), 0.3, 0.3, c0[:1])) == PIFCM_E_INVALID
+    assert status(lambda: ctx.ifcm_solve(x, _P(m=1.0), 0.3, 0.3, c0)) == PIFCM_E_INVALID
+    assert status(lambda: ctx.ifcm_solve(x, _P(V=2), 0.3, 0.3, c0)) == PIFCM_E_UNSUPPORTED
+    assert status(lambda: ctx.ifcm_solve(x, _P(), float("nan"), 0.3, c0)) == PIFCM_E_INVALID
+    bad = x.clone()
+    bad[1, 2, 3] = float("nan")
+    assert status(lambda: ctx.ifcm_solve(bad, _P(), 0.3, 0.3, c0)) == PIFCM_E_NONFINITE
+    raw_bad = torch.tensor([1.0, float("inf"), 2.0], device="cuda")
+    assert status(lambda: ctx.pifcm_normalize(raw_bad)) == PIFCM_E_NONFINITE
+    U = torch.full((x.numel(), 4), 0.3, device="cuda")  # rows sum to 1.2
+    assert status(lambda: ctx.ifcm_solve(x, _P(), 0.3, 0.3, c0, U_in=U)) == PIFCM_E_INVALID
+    Uok = torch.full((x.numel(), 4), 0.25, device="cuda")
+    assert status(lambda: ctx.ifcm_solve(x, _P(), 0.3, 0.3, c0, U_in=Uok, U_out=Uok)) == PIFCM_E_INVALID
+    big = torch.empty(x.numel() * 4 + 1, device="cuda")
+    assert status(lambda: ctx.ifcm_solve(x, _P(), 0.3, 0.3, c0, U_out=big[1:])) == PIFCM_E_INVALID
+    # the context still works after errors
+    g = ctx.ifcm_solve(x, _P(max_iter=2, eps=0.0), 0.3, 0.3, c0)
+    assert g["iters"] == 2 and np.isfinite(g["J"])
