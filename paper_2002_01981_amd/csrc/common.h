@@ -7,18 +7,30 @@
 
 namespace pifcm {
 
-__device__ __forceinline__ float frcp(float v) { return __builtin_amdgcn_rcpf(v); }
+// Global-memory views of pointers read from descriptor tables: loads and
+// stores through them are global (not flat) instructions.
+typedef __attribute__((address_space(1))) float gfloat;
+__device__ __forceinline__ const gfloat* as_global(const float* p) { return (const gfloat*)p; }
+__device__ __forceinline__ gfloat* as_global(float* p) { return (gfloat*)p; }
 
-// Items of a launch are split into 8 contiguous ranges, one per XCD (work
-// groups are dealt to the 8 XCDs round-robin), so tiles that share halos run
-// on the same XCD and meet in its L2.
-__device__ __forceinline__ void item_range(int nitems, int& first, int& end, int& step) {
-  const int per = (nitems + 7) >> 3;
-  const int xcd = blockIdx.x & 7;
-  first = xcd * per + (blockIdx.x >> 3);
-  end = min(nitems, (xcd + 1) * per);
-  step = gridDim.x >> 3;
+// Read-only descriptor data (tables, particle state) through the constant
+// address space: uniform reads become scalar loads.
+template <typename T>
+__device__ __forceinline__ T ld_const(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized descriptors only");
+  typedef const __attribute__((address_space(4))) uint32_t CW;
+  T out;
+  uint32_t* o = reinterpret_cast<uint32_t*>(&out);
+  CW* q = (CW*)p;
+#pragma unroll
+  for (unsigned i = 0; i < sizeof(T) / 4; ++i) o[i] = q[i];
+  return out;
 }
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float frcp(float v) { return __builtin_amdgcn_rcpf(v); }
 
 __device__ __forceinline__ int vol_of_item(const LaunchArgs& a, int it) {
   int b = 0;
@@ -26,12 +38,15 @@ __device__ __forceinline__ int vol_of_item(const LaunchArgs& a, int it) {
   return b;
 }
 
+// Row of C memberships in global memory (16-byte aligned when C % 4 == 0).
 template <int C>
-__device__ __forceinline__ void load_row(const float* __restrict__ p, float (&u)[C]) {
+__device__ __forceinline__ void load_row(const gfloat* p, float (&u)[C]) {
+  typedef __attribute__((address_space(1))) const f4v G4;
+  typedef __attribute__((address_space(1))) const f2v G2;
   if constexpr (C % 4 == 0) {
 #pragma unroll
     for (int q = 0; q < C / 4; ++q) {
-      const float4 v = reinterpret_cast<const float4*>(p)[q];
+      const f4v v = reinterpret_cast<G4*>(p)[q];
       u[4 * q] = v.x;
       u[4 * q + 1] = v.y;
       u[4 * q + 2] = v.z;
@@ -40,7 +55,7 @@ __device__ __forceinline__ void load_row(const float* __restrict__ p, float (&u)
   } else if constexpr (C % 2 == 0) {
 #pragma unroll
     for (int q = 0; q < C / 2; ++q) {
-      const float2 v = reinterpret_cast<const float2*>(p)[q];
+      const f2v v = reinterpret_cast<G2*>(p)[q];
       u[2 * q] = v.x;
       u[2 * q + 1] = v.y;
     }
@@ -51,15 +66,27 @@ __device__ __forceinline__ void load_row(const float* __restrict__ p, float (&u)
 }
 
 template <int C>
-__device__ __forceinline__ void store_row(float* __restrict__ p, const float (&u)[C]) {
+__device__ __forceinline__ void store_row(gfloat* p, const float (&u)[C]) {
+  typedef __attribute__((address_space(1))) f4v G4;
+  typedef __attribute__((address_space(1))) f2v G2;
   if constexpr (C % 4 == 0) {
 #pragma unroll
-    for (int q = 0; q < C / 4; ++q)
-      reinterpret_cast<float4*>(p)[q] = make_float4(u[4 * q], u[4 * q + 1], u[4 * q + 2], u[4 * q + 3]);
+    for (int q = 0; q < C / 4; ++q) {
+      f4v v;
+      v.x = u[4 * q];
+      v.y = u[4 * q + 1];
+      v.z = u[4 * q + 2];
+      v.w = u[4 * q + 3];
+      reinterpret_cast<G4*>(p)[q] = v;
+    }
   } else if constexpr (C % 2 == 0) {
 #pragma unroll
-    for (int q = 0; q < C / 2; ++q)
-      reinterpret_cast<float2*>(p)[q] = make_float2(u[2 * q], u[2 * q + 1]);
+    for (int q = 0; q < C / 2; ++q) {
+      f2v v;
+      v.x = u[2 * q];
+      v.y = u[2 * q + 1];
+      reinterpret_cast<G2*>(p)[q] = v;
+    }
   } else {
 #pragma unroll
     for (int j = 0; j < C; ++j) p[j] = u[j];
@@ -132,15 +159,33 @@ __device__ __forceinline__ void memberships(const float (&d2)[C], float m, float
   }
 }
 
-// ---------------------------------------------------------------- tile end
-// Reduce NV per-lane sums over the work group (fixed butterfly, then waves in
-// order), store them in the pair's slot for this tile, and let the last tile
-// of the pair to finish combine all slots in fp64 and advance the state.
-template <int C, int NT, bool STEP>
-__device__ __forceinline__ void tile_done(const PairDev& pr, int tile, int tiles,
-                                          float (&acc)[STEP ? 2 * C + 1 : 1], float* s_red,
-                                          double* s_redd, int* s_flag) {
-  constexpr int NV = STEP ? 2 * C + 1 : 1;
+// ------------------------------------------------------------ tile sums
+// Every tile of a launch leaves NV fp32 sums in its own slot of the pair's
+// partials ([tile][NV]); a per-pair finalise kernel launched right after adds
+// the slots in fp64 in tile order.  Both reductions have a fixed order, so
+// the results do not depend on scheduling.
+
+// Wave owning a tile: butterfly over the 64 lanes, lane 0 stores the slot.
+template <int NV>
+__device__ __forceinline__ void wave_tile_store(const PairDev& pr, int tile, float (&acc)[NV]) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    float v = acc[k];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    acc[k] = v;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    gfloat* slot = as_global(pr.partials) + (size_t)tile * NV;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) slot[k] = acc[k];
+  }
+}
+
+// Work group owning a tile: butterfly per wave, waves in order through LDS.
+template <int NV, int NT>
+__device__ __forceinline__ void block_tile_store(const PairDev& pr, int tile, float (&acc)[NV],
+                                                 float* s_red) {
   constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -155,76 +200,84 @@ __device__ __forceinline__ void tile_done(const PairDev& pr, int tile, int tiles
     for (int k = 0; k < NV; ++k) s_red[wave * NV + k] = acc[k];
   }
   __syncthreads();
+  if (threadIdx.x < NV) {
+    float s = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += s_red[w * NV + threadIdx.x];
+    as_global(pr.partials)[(size_t)tile * NV + threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// Advance the state of a pair from its fp64 totals (one thread): new centres
+// (eq (3)), J of the iteration's input state (eq (1)) and the stop rule; or,
+// for the objective-only pass, the fitness.
+template <int C, bool STEP>
+__device__ __forceinline__ void finish_pair(SolveState* st, const double* tot) {
+  if constexpr (STEP) {
+    const int t = st->iter + 1;
+    const int par = t & 1;
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const double den = tot[C + j];
+      st->c[par][j] = den > 0.0 ? (float)(tot[j] / den) : st->c[par ^ 1][j];
+    }
+    const double J = tot[2 * C];
+    if (st->J_hist) st->J_hist[t - 1] = J;
+    int stop = 0;
+    if (t >= 2 && st->eps > 0.f && fabs(J - st->J_prev1) <= (double)st->eps * fabs(st->J_prev1))
+      stop = 1;
+    if (t >= st->max_iter) stop = 1;
+    st->J_prev2 = st->J_prev1;
+    st->J_prev1 = J;
+    st->iter = t;
+    st->stop = stop;
+  } else {
+    st->J_eval = tot[0];
+  }
+}
+
+// One work group per pair: add the pair's tile slots in fp64 (thread t takes
+// tiles t, t + 256, ...; then a fixed butterfly and the waves in order) and
+// advance its state.  Pairs that have stopped are left alone.
+template <int C, bool STEP>
+__global__ __launch_bounds__(256) void k_finalize(const LaunchArgs a) {
+  constexpr int NV = STEP ? 2 * C + 1 : 1;
+  __shared__ double s_red[4 * NV];
+  const int pair = blockIdx.x;
+  const PairDev pr = a.pairs[pair];
+  SolveState* st = pr.st;
+  if (STEP && st->stop) return;
+  const VolDev vd = a.vols[pair / a.P];
+  const int tiles = a.use_1d ? vd.tiles1d : vd.tiles;
+  double d[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) d[k] = 0.0;
+  const gfloat* parts = as_global(pr.partials);
+  for (int s = threadIdx.x; s < tiles; s += 256) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) d[k] += (double)parts[(size_t)s * NV + k];
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double v = d[k];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    d[k] = v;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s_red[wave * NV + k] = d[k];
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    float* slot = pr.partials + (size_t)tile * NV;
+    double tot[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      float s = 0.f;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) s += s_red[w * NV + k];
-      slot[k] = s;
-    }
-    __threadfence();
-    const uint32_t prev = atomicAdd(&pr.st->counter, 1u);
-    *s_flag = (prev == (uint32_t)(tiles - 1));
+    for (int k = 0; k < NV; ++k)
+      tot[k] = ((s_red[k] + s_red[NV + k]) + s_red[2 * NV + k]) + s_red[3 * NV + k];
+    finish_pair<C, STEP>(st, tot);
   }
-  __syncthreads();
-  if (*s_flag) {
-    __threadfence();
-    double d[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) d[k] = 0.0;
-    for (int s = threadIdx.x; s < tiles; s += NT) {
-      const float* slot = pr.partials + (size_t)s * NV;
-#pragma unroll
-      for (int k = 0; k < NV; ++k) d[k] += (double)__builtin_nontemporal_load(slot + k);
-    }
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double v = d[k];
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-      d[k] = v;
-    }
-    if (lane == 0) {
-#pragma unroll
-      for (int k = 0; k < NV; ++k) s_redd[wave * NV + k] = d[k];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double tot[NV];
-#pragma unroll
-      for (int k = 0; k < NV; ++k) {
-        tot[k] = 0.0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) tot[k] += s_redd[w * NV + k];
-      }
-      SolveState* st = pr.st;
-      if constexpr (STEP) {
-        const int t = st->iter + 1;
-        const int par = t & 1;
-#pragma unroll
-        for (int j = 0; j < C; ++j) {
-          const double den = tot[C + j];
-          st->c[par][j] = den > 0.0 ? (float)(tot[j] / den) : st->c[par ^ 1][j];  // eq (3)
-        }
-        const double J = tot[2 * C];  // eq (1) of the iteration's input state
-        if (st->J_hist) st->J_hist[t - 1] = J;
-        int stop = 0;
-        if (t >= 2 && st->eps > 0.f && fabs(J - st->J_prev1) <= (double)st->eps * fabs(st->J_prev1))
-          stop = 1;
-        if (t >= st->max_iter) stop = 1;
-        st->J_prev2 = st->J_prev1;
-        st->J_prev1 = J;
-        st->iter = t;
-        st->stop = stop;
-      } else {
-        st->J_eval = tot[0];
-      }
-      st->counter = 0u;
-    }
-  }
-  __syncthreads();
 }
 
 }  // namespace pifcm

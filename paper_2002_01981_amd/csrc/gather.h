@@ -10,27 +10,37 @@
 // (eq (3)).  All of it is fused into k_ifcm_gather: one HBM pass reads x and
 // U^(t) and writes U^(t+1).
 //
-// Data flow of k_ifcm_gather.  A work item is a tile of 64 (x) by TY (y)
-// columns and zc planes of one (volume, particle) pair; each lane owns one
-// (x, y) column and walks it along z.  Each plane of the tile plus a
-// one-voxel halo is staged once in LDS (double-buffered, one barrier per
-// plane) and every lane reads its 3x3 in-plane cells once: they contribute
-// to three voxels of its column at the same time -- z-1 (the plane is its
-// upper neighbour plane), z (its own plane) and z+1 (lower plane).  The
-// partial sums of those three voxels live in a ring of register slots; the
-// voxel z-1 is complete after the plane and is finalised right away.  Plane
-// data is prefetched two planes ahead into registers.
+// Work decomposition.  A work item is a tile of 16 (x) by 4 (y) columns and
+// zc planes of one (volume, particle) pair, owned by ONE wavefront: each
+// lane owns one (x, y) column and walks it along z.  Waves never wait for
+// each other -- each has a private LDS region -- so there is no work-group
+// barrier anywhere in the kernel.  Each plane of the tile plus a one-voxel
+// halo (18 x 6 cells) is staged once in the wave's LDS (double-buffered) and
+// every lane reads its 3x3 in-plane cells once: they contribute to three
+// voxels of its column at the same time -- z-1 (the plane is its upper
+// neighbour plane), z (its own plane) and z+1 (lower plane).  The partial
+// sums of those voxels live in a ring of three register slots; voxel z-1 is
+// complete after the plane and is finalised right away.  The next plane is
+// prefetched into registers while the current one is processed.  Planes away
+// from the tile's first and last ones run a branch-free body unrolled three
+// times so the slot ring rotates by renaming instead of register moves.
 //
 // Arithmetic shortcuts that keep the results those of the equations:
 //   * the denominator of eq (5), sum_k |x_i - x_k|, does not change between
-//     iterations and is precomputed once per volume (k_invariants);
+//     iterations: it is precomputed once per volume as its inverse g_inv;
 //   * sum_j H_ij = 1 when the rows of U sum to 1, so the last cluster's H is
 //     1 - sum of the others (rows of caller-supplied U are validated);
+//   * a voxel whose neighbours all share its intensity takes the mean of
+//     their memberships in eq (5); it is stored with g_inv = -1 / n_valid and
+//     its centre value shifted by -1 when forming g, so every g_ik of it is
+//     exactly 1 and the gather yields the mean with no branch;
 //   * eq (7)'s weights depend only on the offset class (face, edge, corner
 //     in the plane and one plane off), so per plane the squared memberships
 //     are summed per class once and weighted afterwards;
-//   * the denominator of eq (7) is a function of which neighbours exist,
-//     computed from the column position and the plane count.
+//   * the denominator of eq (7) depends only on which neighbours exist and is
+//     formed from the column position and the plane index;
+//   * cells outside the volume are staged with u = 0, so they add nothing to
+//     any sum.
 // Sums over voxels are per-lane in fp32, reduced per tile in a fixed
 // butterfly order, and combined over tiles in fp64 by the last tile of the
 // pair to finish (no floating-point atomics: results are bit-reproducible).
@@ -39,86 +49,91 @@
 
 namespace pifcm {
 
-// ------------------------------------------------------------ fused gather
+constexpr int kWX = 16, kWY = 4;               // wave tile (columns)
+constexpr int kHX = kWX + 2, kHY = kWY + 2;    // staged plane with halo
+constexpr int kNCell = kHX * kHY;              // 108 cells
+constexpr int kNHalo = kNCell - 64;            // 44 halo cells, one per lane
+
 #ifndef PIFCM_GATHER_ATTR
 #define PIFCM_GATHER_ATTR
 #endif
-template <int C, bool M2, int TY, bool STEP>
-__global__ __launch_bounds__(64 * TY) PIFCM_GATHER_ATTR void k_ifcm_gather(const LaunchArgs a) {
-  constexpr int NT = 64 * TY;
+
+template <int C, bool M2, int NW, bool STEP>
+__global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const LaunchArgs a) {
   constexpr int CP = (C + 3) / 4 * 4;
-  constexpr int WD = kTX + 2;                // halo tile width
-  constexpr int NCELL = WD * (TY + 2);
-  constexpr int NHALO = 2 * WD + 2 * TY;
-  constexpr int HPT = (NHALO + NT - 1) / NT;  // halo cells per lane
-  constexpr int CH = C - 1;                   // clusters whose H is gathered
+  constexpr int CH = C - 1;  // clusters whose H is gathered
   constexpr int NV = STEP ? 2 * C + 1 : 1;
 
-  __shared__ float s_x[2][NCELL];
-  __shared__ __align__(16) float s_u[2][NCELL * CP];
-  __shared__ float s_red[(NT / 64) * NV];
-  __shared__ double s_redd[(NT / 64) * NV];
-  __shared__ int s_flag;
+  __shared__ float s_x[NW][2][kNCell];
+  __shared__ __align__(16) float s_u[NW][2][kNCell * CP];
 
-  const int tid = threadIdx.x;
-  const int tx = tid & 63, ty = tid >> 6;
-  const int own_cell = (ty + 1) * WD + (tx + 1);
+  const int lane = threadIdx.x & 63;
+  // The wave index is uniform across the wave; say so, so that every value
+  // derived from it (the work item, its pointers and parameters) stays in
+  // scalar registers.
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tx = lane & (kWX - 1), ty = lane / kWX;
+  const int own_cell = (ty + 1) * kHX + (tx + 1);
+  int hcx, hcy;
+  if (lane < kHX) { hcy = 0; hcx = lane; }
+  else if (lane < 2 * kHX) { hcy = kHY - 1; hcx = lane - kHX; }
+  else if (lane < 2 * kHX + kWY) { hcy = 1 + lane - 2 * kHX; hcx = 0; }
+  else { hcy = 1 + lane - 2 * kHX - kWY; hcx = kHX - 1; }
+  const bool hlane = lane < kNHalo;
+  const int halo_cell = hlane ? hcy * kHX + hcx : 0;
   // eq (7) weights by offset class: in-plane edge / corner (q = 1, 2) and
   // off-plane centre / edge / corner (q = 1, 2, 3); q^2 or q.
   const float wEa = 1.f, wCa = a.q2_sqdist ? 2.f : 4.f;
   const float wPb = 1.f, wEb = a.q2_sqdist ? 2.f : 4.f, wCb = a.q2_sqdist ? 3.f : 9.f;
 
-  int h_cy[HPT], h_cx[HPT];
-  bool h_ok[HPT];
-#pragma unroll
-  for (int k = 0; k < HPT; ++k) {
-    const int h = tid + k * NT;
-    h_ok[k] = h < NHALO;
-    int cy, cx;
-    if (h < WD) { cy = 0; cx = h; }
-    else if (h < 2 * WD) { cy = TY + 1; cx = h - WD; }
-    else if (h < 2 * WD + TY) { cy = 1 + (h - 2 * WD); cx = 0; }
-    else { cy = 1 + (h - 2 * WD - TY); cx = WD - 1; }
-    h_cy[k] = cy;
-    h_cx[k] = cx;
-  }
-
-  int first, end, step;
-  item_range(a.nitems, first, end, step);
-  for (int it = first; it < end; it += step) {
+  // Items: 8 contiguous ranges, one per XCD (work groups go to the XCDs
+  // round-robin), walked by that XCD's waves so neighbouring tiles share L2.
+  const int per = (a.nitems + 7) >> 3;
+  const int xcd = blockIdx.x & 7;
+  const int it_end = min(a.nitems, (xcd + 1) * per);
+  const int it_step = (gridDim.x >> 3) * NW;
+  for (int it = xcd * per + (blockIdx.x >> 3) * NW + wave; it < it_end; it += it_step) {
     const int b = vol_of_item(a, it);
-    const VolDev vd = a.vols[b];
+    const VolDev vd = ld_const(a.vols + b);
     const int r = it - a.item_begin[b];
     const int pidx = r / vd.tiles;
     const int tile = r - pidx * vd.tiles;
-    const PairDev pr = a.pairs[b * a.P + pidx];
-    SolveState* st = pr.st;
-    if (STEP && st->stop) continue;
-    const int t = STEP ? st->iter + 1 : st->iter;
-    const float* __restrict__ Uin = STEP ? u_in_of(pr, t) : u_state_of(pr, t);
-    float* __restrict__ Uout = STEP ? u_out_of(pr, t) : nullptr;
+    const PairDev pr = ld_const(a.pairs + b * a.P + pidx);
+    const SolveState* st = pr.st;
+    if (STEP && ld_const(&st->stop)) continue;
+    const int t = STEP ? ld_const(&st->iter) + 1 : ld_const(&st->iter);
+    const float* Uin = STEP ? u_in_of(pr, t) : u_state_of(pr, t);
+    float* Uout = STEP ? u_out_of(pr, t) : nullptr;
     float cj[C];
 #pragma unroll
-    for (int j = 0; j < C; ++j) cj[j] = st->c[(STEP ? t - 1 : t) & 1][j];
-    const float lam = st->lam, xi = st->xi;
-    const float* __restrict__ X = vd.x;
-    const float* __restrict__ IG = vd.invg;
+    for (int j = 0; j < C; ++j) cj[j] = ld_const(&st->c[(STEP ? t - 1 : t) & 1][j]);
+    const float lam = ld_const(&st->lam), xi = ld_const(&st->xi);
     const int nx = vd.nx, ny = vd.ny, nz = vd.nz;
 
     const int txi = tile % vd.ntx;
     const int rest = tile / vd.ntx;
     const int tyi = rest % vd.nty;
     const int tzi = rest / vd.nty;
-    const int x0 = txi * kTX, y0 = tyi * TY;
+    const int x0 = txi * kWX, y0 = tyi * kWY;
     const int zlo = tzi * vd.zc, zhi = min(zlo + vd.zc, nz);
     const int gx = x0 + tx, gy = y0 + ty;
     const bool active = gx < nx && gy < ny;
-    const size_t plane_sz = (size_t)nx * ny;
-    const size_t own_xy = (size_t)gy * nx + gx;
+    const int hx = x0 - 1 + hcx, hy = y0 - 1 + hcy;
+    const bool hvalid = hlane && hx >= 0 && hx < nx && hy >= 0 && hy < ny;
+    // 32-bit offsets from the first staged plane of the tile (the host keeps
+    // (zc + 2) * nx * ny * C * 4 below 2^31).
+    const uint32_t psz = (uint32_t)nx * (uint32_t)ny;
+    const int zb = max(zlo - 1, 0);
+    const gfloat* Xb = as_global(vd.x) + (size_t)zb * psz;
+    const gfloat* Gb = as_global(vd.invg) + (size_t)zb * psz;
+    const gfloat* Ub = as_global(Uin) + (size_t)zb * psz * C;
+    gfloat* Ob = STEP ? as_global(Uout) + (size_t)zb * psz * C : nullptr;
+    const uint32_t own_xy = active ? (uint32_t)gy * nx + gx : 0u;
+    const uint32_t halo_xy = hvalid ? (uint32_t)hy * nx + hx : 0u;
 
-    // Denominator of eq (7) for this column: in-plane neighbours give
-    // edges e and corners e_x * e_y, each of the az existing off-planes a
-    // centre, e edges and e_x * e_y corners.
+    // Denominator of eq (7): in-plane edges e and corners e_x * e_y, plus for
+    // each of the az existing off-planes a centre, e edges and e_x * e_y
+    // corners.
     float invQ[3];
     {
       const int ex = (gx > 0) + (gx < nx - 1), ey = (gy > 0) + (gy < ny - 1);
@@ -131,111 +146,89 @@ __global__ __launch_bounds__(64 * TY) PIFCM_GATHER_ATTR void k_ifcm_gather(const
       }
     }
 
-    // Register sets for planes in flight (two planes ahead).
-    float rx[2], rg[2], ru[2][C], rhx[2][HPT], rhu[2][HPT][C];
-    auto load_plane = [&](int q, float& ox, float& og, float (&ou)[C], float (&hx)[HPT],
-                          float (&hu)[HPT][C]) __attribute__((always_inline)) {
+    // Prefetch registers of the next plane.
+    float rx, rg, ru[C], rhx, rhu[C];
+    auto load_plane = [&](int q) __attribute__((always_inline)) {
       const bool pv = q >= 0 && q < nz;
-      const size_t base = (size_t)q * plane_sz;
+      const uint32_t pofs = (uint32_t)(q - zb) * psz;
       if (pv && active) {
-        const size_t i = base + own_xy;
-        ox = X[i];
-        og = IG[i];
-        load_row<C>(Uin + i * C, ou);
+        const uint32_t o = pofs + own_xy;
+        rx = Xb[o];
+        rg = Gb[o];
+        load_row<C>(Ub + o * C, ru);
       } else {
-        ox = 0.f;
-        og = 1.f;
+        rx = 0.f;
+        rg = 1.f;
 #pragma unroll
-        for (int j = 0; j < C; ++j) ou[j] = 0.f;
+        for (int j = 0; j < C; ++j) ru[j] = 0.f;
       }
+      if (pv && hvalid) {
+        const uint32_t o = pofs + halo_xy;
+        rhx = Xb[o];
+        load_row<C>(Ub + o * C, rhu);
+      } else {
+        rhx = 0.f;
 #pragma unroll
-      for (int k = 0; k < HPT; ++k) {
-        const int hx_ = x0 - 1 + h_cx[k], hy_ = y0 - 1 + h_cy[k];
-        const bool ok = pv && h_ok[k] && hx_ >= 0 && hx_ < nx && hy_ >= 0 && hy_ < ny;
-        if (ok) {
-          const size_t i = base + (size_t)hy_ * nx + hx_;
-          hx[k] = X[i];
-          load_row<C>(Uin + i * C, hu[k]);
-        } else {
-          hx[k] = 0.f;
-#pragma unroll
-          for (int j = 0; j < C; ++j) hu[k][j] = 0.f;
-        }
+        for (int j = 0; j < C; ++j) rhu[j] = 0.f;
       }
     };
-    auto store_plane = [&](int buf, const float& ox, const float (&ou)[C], const float (&hx)[HPT],
-                           const float (&hu)[HPT][C]) __attribute__((always_inline)) {
-      s_x[buf][own_cell] = ox;
-      lds_cell_store<C, CP>(&s_u[buf][own_cell * CP], ou);
-#pragma unroll
-      for (int k = 0; k < HPT; ++k) {
-        if (h_ok[k]) {
-          const int cell = h_cy[k] * WD + h_cx[k];
-          s_x[buf][cell] = hx[k];
-          lds_cell_store<C, CP>(&s_u[buf][cell * CP], hu[k]);
-        }
+    auto store_plane = [&](int buf) __attribute__((always_inline)) {
+      float* sx = s_x[wave][buf];
+      float* su = s_u[wave][buf];
+      sx[own_cell] = rx;
+      lds_cell_store<C, CP>(su + own_cell * CP, ru);
+      if (hlane) {
+        sx[halo_cell] = rhx;
+        lds_cell_store<C, CP>(su + halo_cell * CP, rhu);
       }
     };
 
-    // Slots of the three voxels in flight.
-    float hn[3][CH > 0 ? CH : 1], fn[3][C], xs[3], gs[3], us[3][C];
+    // Slots of the three voxels in flight: gathered H numerators, F class
+    // sums, centre value for g (xs), intensity (xt), |g_inv| (gs), input
+    // memberships (us).
+    float hn[3][CH], fn[3][C], xs[3], xt[3], gs[3], us[3][C];
     float acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.f;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      xs[s] = xt[s] = 0.f;
+      gs[s] = 0.f;
+#pragma unroll
+      for (int j = 0; j < CH; ++j) hn[s][j] = 0.f;
+#pragma unroll
+      for (int j = 0; j < C; ++j) fn[s][j] = us[s][j] = 0.f;
+    }
 
-    // Finalise voxel z of slot S: eqs (5)/(7) ratios, (4), (1), (2), (3).
-    auto finalize = [&](int z, const float (&h)[CH > 0 ? CH : 1], const float (&f)[C], float xv,
-                        float ig, const float (&uo)[C]) __attribute__((always_inline)) {
+    // Finalise voxel z held in slot S: eqs (5)/(7) ratios, (4), (1), (2), (3).
+    auto finalize = [&](int z, auto Sc) __attribute__((always_inline)) {
+      constexpr int S = decltype(Sc)::value;
       if (!active) return;
-      const int az = (z > 0) + (z < nz - 1);
-      const float iq = invQ[az];
-      float H[C];
-      if (__builtin_expect(ig >= 0.f, 1)) {
-        float sh = 0.f;
+      const float iq = invQ[(z > 0) + (z < nz - 1)];
+      const float ig = gs[S];
+      // a_j = 1 - lambda H_j - xi F_j with H_j = hn_j * ig, F_j = fn_j * iq.
+      const float lg = -lam * ig, xq = -xi * iq;
+      float sh = 0.f;
 #pragma unroll
-        for (int j = 0; j < CH; ++j) {
-          H[j] = h[j] * ig;
-          sh += H[j];
-        }
-        H[C - 1] = 1.f - sh;
-      } else {
-        // Every neighbour has the voxel's own intensity: eq (5) in the
-        // equal-weight limit, the plain mean of the neighbours' memberships.
-        float sum[C];
-#pragma unroll
-        for (int j = 0; j < C; ++j) sum[j] = 0.f;
-        int cnt = 0;
-        for (int dz = -1; dz <= 1; ++dz)
-          for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-              const int X2 = gx + dx, Y2 = gy + dy, Z2 = z + dz;
-              if ((dx | dy | dz) == 0 || X2 < 0 || X2 >= nx || Y2 < 0 || Y2 >= ny || Z2 < 0 ||
-                  Z2 >= nz)
-                continue;
-              float u2[C];
-              load_row<C>(Uin + (((size_t)Z2 * ny + Y2) * nx + X2) * C, u2);
-#pragma unroll
-              for (int j = 0; j < C; ++j) sum[j] += u2[j];
-              ++cnt;
-            }
-        const float ic = cnt > 0 ? 1.f / (float)cnt : 0.f;
-#pragma unroll
-        for (int j = 0; j < C; ++j) H[j] = sum[j] * ic;
-      }
+      for (int j = 0; j < CH; ++j) sh += hn[S][j];
+      // Last cluster by sum_j H_ij = 1 (0 when the voxel has no neighbour).
+      const float hlast = ig != 0.f ? fmaf(-ig, sh, 1.f) : 0.f;
+      const float xv = xt[S];
       float d2[C];
       float Jv = 0.f;
 #pragma unroll
       for (int j = 0; j < C; ++j) {
-        const float av = fmaf(-lam, H[j], fmaf(-xi, f[j] * iq, 1.f));  // eq (4) factor
+        const float ah = j < CH ? fmaf(lg, hn[S][j < CH ? j : 0], 1.f) : fmaf(-lam, hlast, 1.f);
+        const float av = fmaf(xq, fn[S][j], ah);  // eq (4) factor
         const float dd = xv - cj[j];
         d2[j] = fmaxf(dd * dd * av, kDFloor);
-        Jv = fmaf(pow_m<M2>(uo[j], a.m), d2[j], Jv);  // eq (1)
+        Jv = fmaf(pow_m<M2>(us[S][j], a.m), d2[j], Jv);  // eq (1)
       }
       if constexpr (STEP) {
         float un[C];
         memberships<C, M2>(d2, a.m, un);  // eq (2)
-        const size_t i = (size_t)z * plane_sz + own_xy;
-        store_row<C>(Uout + i * C, un);
+        const uint32_t o = (uint32_t)(z - zb) * psz + own_xy;
+        store_row<C>(Ob + o * C, un);
 #pragma unroll
         for (int j = 0; j < C; ++j) {
           const float w = pow_m<M2>(un[j], a.m);
@@ -249,30 +242,37 @@ __global__ __launch_bounds__(64 * TY) PIFCM_GATHER_ATTR void k_ifcm_gather(const
     };
 
     // One plane p: contributions of its 3x3 cells to voxels p-1 (slot SA),
-    // p (SB), p+1 (SC); then finalise p-1, stage plane p+1, prefetch p+3.
-    auto plane = [&](int p, auto SAc, auto SBc, auto SCc, auto S1c) __attribute__((always_inline)) {
+    // p (SB) and p+1 (SC); finalise p-1; stage plane p+1; prefetch p+2.
+    // GEN: the tile's first / last planes, with the validity tests.
+    auto plane = [&](int p, auto SAc, auto SBc, auto SCc, auto GENc) __attribute__((always_inline)) {
       constexpr int SA = decltype(SAc)::value, SB = decltype(SBc)::value;
-      constexpr int SC = decltype(SCc)::value, S1 = decltype(S1c)::value;
-      __syncthreads();
-      const bool pv = p >= 0 && p < nz;
-      const bool doA = p - 1 >= zlo;
-      const bool doB = p >= zlo && p < zhi;
-      const bool doC = p + 1 < zhi;
+      constexpr int SC = decltype(SCc)::value;
+      constexpr bool GEN = decltype(GENc)::value;
+      const bool pv = !GEN || (p >= 0 && p < nz);
+      const bool doA = !GEN || p - 1 >= zlo;
+      const bool doB = !GEN || (p >= zlo && p < zhi);
+      const bool doC = !GEN || p + 1 < zhi;
+      __builtin_amdgcn_wave_barrier();
+#ifdef PIFCM_PLANE_SCHED_FENCE
+      __builtin_amdgcn_sched_barrier(0);
+#endif
+      // Centre value of voxel p+1 (from the prefetched plane).
+      const float xC = rg < 0.f ? rx - 1.f : rx;
       if (pv) {
-        const float* __restrict__ sx = s_x[p & 1];
-        const float* __restrict__ su = s_u[p & 1];
+        const float* __restrict__ sx = s_x[wave][p & 1];
+        const float* __restrict__ su = s_u[wave][p & 1];
         float E[C], Co[C], Pc[C];
-        float hA[CH > 0 ? CH : 1], hB[CH > 0 ? CH : 1], hC[CH > 0 ? CH : 1];
+        float hA[CH], hB[CH], hC[CH];
 #pragma unroll
         for (int j = 0; j < C; ++j) E[j] = Co[j] = Pc[j] = 0.f;
 #pragma unroll
         for (int j = 0; j < CH; ++j) hA[j] = hB[j] = hC[j] = 0.f;
-        const float xA = xs[SA], xB = xs[SB], xC = rx[S1];
+        const float xA = xs[SA], xB = xs[SB];
 #pragma unroll
         for (int dy = -1; dy <= 1; ++dy) {
 #pragma unroll
           for (int dx = -1; dx <= 1; ++dx) {
-            const int cell = own_cell + dy * WD + dx;
+            const int cell = own_cell + dy * kHX + dx;
             const float xk = sx[cell];
             float u[C];
             lds_cell_load<C, CP>(su + cell * CP, u);
@@ -330,96 +330,106 @@ __global__ __launch_bounds__(64 * TY) PIFCM_GATHER_ATTR void k_ifcm_gather(const
 #pragma unroll
         for (int j = 0; j < C; ++j) fn[SC][j] = 0.f;
       }
-      if (doA) finalize(p - 1, hn[SA], fn[SA], xs[SA], gs[SA], us[SA]);
-      if (p + 1 <= zhi) {
-        store_plane((p + 1) & 1, rx[S1], ru[S1], rhx[S1], rhu[S1]);
-        xs[SC] = rx[S1];
-        gs[SC] = rg[S1];
+      if (doA) finalize(p - 1, SAc);
+      if (!GEN || p + 1 <= zhi) {
+        store_plane((p + 1) & 1);
+        xs[SC] = xC;
+        xt[SC] = rx;
+        gs[SC] = fabsf(rg);
 #pragma unroll
-        for (int j = 0; j < C; ++j) us[SC][j] = ru[S1][j];
-        if (p + 3 <= zhi) load_plane(p + 3, rx[S1], rg[S1], ru[S1], rhx[S1], rhu[S1]);
+        for (int j = 0; j < C; ++j) us[SC][j] = ru[j];
+        if (!GEN || p + 2 <= zhi) load_plane(p + 2);
       }
     };
 
-    // Prologue: planes zlo-1 (staged), zlo and zlo+1 (in flight).
-    load_plane(zlo - 1, rx[0], rg[0], ru[0], rhx[0], rhu[0]);
-    load_plane(zlo, rx[1], rg[1], ru[1], rhx[1], rhu[1]);
-    __syncthreads();  // previous item's last plane reads are done
-    store_plane((zlo - 1) & 1, rx[0], ru[0], rhx[0], rhu[0]);
-    if (zlo + 1 <= zhi) load_plane(zlo + 1, rx[0], rg[0], ru[0], rhx[0], rhu[0]);
+    // Canonical slot ring: slot 0 = voxel p-1, 1 = p, 2 = p+1.  After a plane
+    // processed with the canonical slots, move the ring down by one.
+    auto shift = [&]() __attribute__((always_inline)) {
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      xs[s] = 0.f;
-      gs[s] = 1.f;
+      for (int s = 0; s < 2; ++s) {
+        xs[s] = xs[s + 1];
+        xt[s] = xt[s + 1];
+        gs[s] = gs[s + 1];
 #pragma unroll
-      for (int j = 0; j < CH; ++j) hn[s][j] = 0.f;
+        for (int j = 0; j < CH; ++j) hn[s][j] = hn[s + 1][j];
 #pragma unroll
-      for (int j = 0; j < C; ++j) fn[s][j] = us[s][j] = 0.f;
-    }
+        for (int j = 0; j < C; ++j) {
+          fn[s][j] = fn[s + 1][j];
+          us[s][j] = us[s + 1][j];
+        }
+      }
+    };
 
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
     using I2 = std::integral_constant<int, 2>;
-    for (int p = zlo - 1; p <= zhi; p += 6) {
-      plane(p, I2{}, I0{}, I1{}, I1{});
-      if (p + 1 > zhi) break;
-      plane(p + 1, I0{}, I1{}, I2{}, I0{});
-      if (p + 2 > zhi) break;
-      plane(p + 2, I1{}, I2{}, I0{}, I1{});
-      if (p + 3 > zhi) break;
-      plane(p + 3, I2{}, I0{}, I1{}, I0{});
-      if (p + 4 > zhi) break;
-      plane(p + 4, I0{}, I1{}, I2{}, I1{});
-      if (p + 5 > zhi) break;
-      plane(p + 5, I1{}, I2{}, I0{}, I0{});
+    using Gen = std::integral_constant<bool, true>;
+    using Steady = std::integral_constant<bool, false>;
+
+    // Prologue: stage plane zlo-1 (zeros outside the volume), prefetch zlo.
+    load_plane(zlo - 1);
+    store_plane((zlo - 1) & 1);
+    load_plane(zlo);
+    int p = zlo - 1;
+    while (p <= zhi) {
+      if (p > zlo && p + 4 <= zhi) {
+        // Three interior planes: every test is true; slots rotate by name.
+        plane(p, I0{}, I1{}, I2{}, Steady{});
+        plane(p + 1, I1{}, I2{}, I0{}, Steady{});
+        plane(p + 2, I2{}, I0{}, I1{}, Steady{});
+        p += 3;
+      } else {
+        plane(p, I0{}, I1{}, I2{}, Gen{});
+        shift();
+        p += 1;
+      }
     }
 
-    tile_done<C, NT, STEP>(pr, tile, vd.tiles, acc, s_red, s_redd, &s_flag);
+    wave_tile_store<NV>(pr, tile, acc);
   }
 }
 
-
-// Launch / occupancy of one C.  TY (rows per tile) variants exist only where
-// ALL_TY is set (the C = 4 fast path); elsewhere TY = 4.
-template <int C, bool M2, int TY>
+// Launch / occupancy of one C with NW waves per work group.  NW variants
+// exist only where ALL_NW is set (the C = 4 fast path); elsewhere NW = 4.
+template <int C, bool M2, int NW>
 static hipError_t launch_gather_ct(const LaunchArgs& a, int grid, bool step, hipStream_t s) {
-  if (step) hipLaunchKernelGGL((k_ifcm_gather<C, M2, TY, true>), dim3(grid), dim3(64 * TY), 0, s, a);
-  else hipLaunchKernelGGL((k_ifcm_gather<C, M2, TY, false>), dim3(grid), dim3(64 * TY), 0, s, a);
+  if (step) hipLaunchKernelGGL((k_ifcm_gather<C, M2, NW, true>), dim3(grid), dim3(64 * NW), 0, s, a);
+  else hipLaunchKernelGGL((k_ifcm_gather<C, M2, NW, false>), dim3(grid), dim3(64 * NW), 0, s, a);
   return hipGetLastError();
 }
 
-template <int C, bool M2, int TY>
+template <int C, bool M2, int NW>
 static int occ_gather_ct(bool step) {
   int n = 0;
-  const void* f = step ? reinterpret_cast<const void*>(&k_ifcm_gather<C, M2, TY, true>)
-                       : reinterpret_cast<const void*>(&k_ifcm_gather<C, M2, TY, false>);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64 * TY, 0) != hipSuccess) n = 1;
+  const void* f = step ? reinterpret_cast<const void*>(&k_ifcm_gather<C, M2, NW, true>)
+                       : reinterpret_cast<const void*>(&k_ifcm_gather<C, M2, NW, false>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64 * NW, 0) != hipSuccess) n = 1;
   return std::max(n, 1);
 }
 
-template <int C, bool ALL_TY>
-static hipError_t launch_gather_one(const LaunchArgs& a, int grid, int ty, bool m2, bool step,
+template <int C, bool ALL_NW>
+static hipError_t launch_gather_one(const LaunchArgs& a, int grid, int nw, bool m2, bool step,
                                     hipStream_t s) {
-  if constexpr (ALL_TY) {
-    switch (ty) {
+  if constexpr (ALL_NW) {
+    switch (nw) {
+      case 1: return m2 ? launch_gather_ct<C, true, 1>(a, grid, step, s) : launch_gather_ct<C, false, 1>(a, grid, step, s);
       case 2: return m2 ? launch_gather_ct<C, true, 2>(a, grid, step, s) : launch_gather_ct<C, false, 2>(a, grid, step, s);
       case 4: return m2 ? launch_gather_ct<C, true, 4>(a, grid, step, s) : launch_gather_ct<C, false, 4>(a, grid, step, s);
-      case 8: return m2 ? launch_gather_ct<C, true, 8>(a, grid, step, s) : launch_gather_ct<C, false, 8>(a, grid, step, s);
       default: return hipErrorInvalidValue;
     }
   } else {
-    if (ty != 4) return hipErrorInvalidValue;
+    if (nw != 4) return hipErrorInvalidValue;
     return m2 ? launch_gather_ct<C, true, 4>(a, grid, step, s) : launch_gather_ct<C, false, 4>(a, grid, step, s);
   }
 }
 
-template <int C, bool ALL_TY>
-static int occ_gather_one(int ty, bool m2, bool step) {
-  if constexpr (ALL_TY) {
-    switch (ty) {
+template <int C, bool ALL_NW>
+static int occ_gather_one(int nw, bool m2, bool step) {
+  if constexpr (ALL_NW) {
+    switch (nw) {
+      case 1: return m2 ? occ_gather_ct<C, true, 1>(step) : occ_gather_ct<C, false, 1>(step);
       case 2: return m2 ? occ_gather_ct<C, true, 2>(step) : occ_gather_ct<C, false, 2>(step);
       case 4: return m2 ? occ_gather_ct<C, true, 4>(step) : occ_gather_ct<C, false, 4>(step);
-      case 8: return m2 ? occ_gather_ct<C, true, 8>(step) : occ_gather_ct<C, false, 8>(step);
       default: return 1;
     }
   } else {
@@ -428,11 +438,11 @@ static int occ_gather_one(int ty, bool m2, bool step) {
 }
 
 // One translation unit per group of C defines these for its C values.
-#define PIFCM_DEFINE_GATHER(c, all_ty)                                                     \
-  hipError_t launch_gather_C##c(const LaunchArgs& a, int grid, int ty, bool m2, bool step, \
+#define PIFCM_DEFINE_GATHER(c, all_nw)                                                     \
+  hipError_t launch_gather_C##c(const LaunchArgs& a, int grid, int nw, bool m2, bool step, \
                                 hipStream_t s) {                                           \
-    return launch_gather_one<c, all_ty>(a, grid, ty, m2, step, s);                         \
+    return launch_gather_one<c, all_nw>(a, grid, nw, m2, step, s);                         \
   }                                                                                        \
-  int occ_gather_C##c(int ty, bool m2, bool step) { return occ_gather_one<c, all_ty>(ty, m2, step); }
+  int occ_gather_C##c(int nw, bool m2, bool step) { return occ_gather_one<c, all_nw>(nw, m2, step); }
 
 }  // namespace pifcm

@@ -8,7 +8,8 @@ namespace pifcm {
 
 constexpr int kMaxC = 16;         // clusters supported
 constexpr int kMaxBatchVols = 32; // volumes in one batched launch
-constexpr int kTX = 64;           // tile width along x = one wavefront
+constexpr int kWaveTileX = 16;    // columns of a fused-step tile along x
+constexpr int kWaveTileY = 4;     // and along y (16 x 4 = one wavefront)
 constexpr float kDFloor = 1e-12f; // floor of the squared distance of eq (4)
 constexpr int kFcmVoxPerThread = 8;
 
@@ -31,7 +32,8 @@ struct alignas(64) SolveState {
 // One volume of a launch.
 struct VolDev {
   const float* x;      // [nz][ny][nx] normalised intensities
-  const float* invg;   // [nz][ny][nx] 1 / sum_k |x_i - x_k| (< 0: all equal)
+  const float* invg;   // [nz][ny][nx] 1 / sum_k |x_i - x_k|; -1 / n_valid when
+                       // every neighbour has the voxel's intensity; 0 if none
   int32_t nx, ny, nz;
   int32_t zc;          // planes per tile
   int32_t ntx, nty, ntz;

@@ -35,8 +35,8 @@ struct GraphCache {
 };
 
 struct TileShape {
-  int ty = 4;
-  int zc = 32;
+  int nw = 4;   // wavefronts per work group of the fused step
+  int zc = 32;  // planes per tile
 };
 
 constexpr int kChunk = 8;            // iterations between stop-flag reads
@@ -182,12 +182,20 @@ pifcm_status check_volume(pifcm_ctx* ctx, const pifcm_volume* v) {
 
 size_t nvox(const pifcm_volume& v) { return (size_t)v.nx * v.ny * v.nz; }
 
+// Largest plane count per tile such that the 32-bit in-tile offsets of the
+// fused step stay below 2^31 bytes: (zc + 2) * nx * ny * C * 4 < 2^31.
+int max_zc(const pifcm_volume& v, int C) {
+  const double per_plane = (double)v.nx * v.ny * C * 4.0;
+  const double z = std::floor((2147483647.0 / per_plane)) - 2.0;
+  return (int)std::max(0.0, std::min(z, (double)v.nz));
+}
+
 TileShape shape_for(pifcm_ctx* ctx, int C, bool m2, const pifcm_volume& v) {
-  auto it = ctx->tuned.find(std::make_tuple(C, (int)m2, v.nx, v.ny, v.nz));
-  if (it != ctx->tuned.end()) return it->second;
   TileShape t;
-  t.ty = 4;
-  t.zc = std::min(v.nz, 32);
+  auto it = ctx->tuned.find(std::make_tuple(C, (int)m2, v.nx, v.ny, v.nz));
+  if (it != ctx->tuned.end()) t = it->second;
+  else t.zc = std::min(v.nz, 32);
+  t.zc = std::max(1, std::min(t.zc, max_zc(v, C)));
   return t;
 }
 
@@ -199,8 +207,8 @@ VolDev make_vol(const pifcm_volume& v, const float* invg, TileShape ts) {
   d.ny = v.ny;
   d.nz = v.nz;
   d.zc = std::max(1, std::min(ts.zc, v.nz));
-  d.ntx = (v.nx + kTX - 1) / kTX;
-  d.nty = (v.ny + ts.ty - 1) / ts.ty;
+  d.ntx = (v.nx + kWaveTileX - 1) / kWaveTileX;
+  d.nty = (v.ny + kWaveTileY - 1) / kWaveTileY;
   d.ntz = (v.nz + d.zc - 1) / d.zc;
   d.tiles = d.ntx * d.nty * d.ntz;
   const size_t per = (size_t)256 * kFcmVoxPerThread;
@@ -208,10 +216,15 @@ VolDev make_vol(const pifcm_volume& v, const float* invg, TileShape ts) {
   return d;
 }
 
-int grid_for(pifcm_ctx* ctx, int nitems, int occupancy) {
+// Work groups for `nitems` work items, `per_group` items in flight per work
+// group (waves of the fused step, 1 for the pointwise kernels): one item per
+// slot when they all fit in 8 waves of resident groups, else a persistent
+// grid of the resident groups.  Always a multiple of 8 (one share per XCD).
+int grid_for(pifcm_ctx* ctx, int nitems, int occupancy, int per_group = 1) {
   const long resident = (long)occupancy * ctx->num_cu;
+  const long groups = ((long)nitems + per_group - 1) / per_group;
   long g;
-  if (nitems <= 8 * resident) g = ((long)nitems + 7) / 8 * 8;
+  if (groups <= 8 * resident) g = (groups + 7) / 8 * 8;
   else g = resident / 8 * 8;
   return (int)std::max<long>(8, g);
 }
@@ -263,9 +276,13 @@ SolveState init_state(const float* c0, int C, float lam, float xi, const pifcm_p
   return s;
 }
 
-hipError_t launch_step(int C, const LaunchArgs& a, int grid, int ty, bool m2, bool fcm, bool step,
+// One iteration (step) or the objective-only pass: the tile kernel, then the
+// per-pair finalise that adds the tile sums and advances the state.
+hipError_t launch_step(int C, const LaunchArgs& a, int grid, int nw, bool m2, bool fcm, bool step,
                        hipStream_t s) {
-  return fcm ? launch_fcm(C, a, grid, m2, step, s) : launch_gather(C, a, grid, ty, m2, step, s);
+  hipError_t e = fcm ? launch_fcm(C, a, grid, m2, step, s) : launch_gather(C, a, grid, nw, m2, step, s);
+  if (e != hipSuccess) return e;
+  return launch_finalize(C, a, a.nvol * a.P, step, s);
 }
 
 LaunchArgs make_args(const VolDev* vols_dev, const PairDev* pairs_dev, const std::vector<VolDev>& vh,
@@ -447,14 +464,14 @@ pifcm_status solve_impl(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_par
   if (!U_in) HIPCHK(launch_init_u(C, vol->x, N, st_dev, p->m, m2, ubuf, ctx->s));
 
   LaunchArgs a = make_args((const VolDev*)ctx->tvol.p, (const PairDev*)ctx->tpair.p, vh, 1, 1, fcm, p);
-  const int occ = fcm ? fcm_occupancy(C, m2, true) : gather_occupancy(C, ts.ty, m2, true);
-  const int grid = grid_for(ctx, a.nitems, occ);
+  const int occ = fcm ? fcm_occupancy(C, m2, true) : gather_occupancy(C, ts.nw, m2, true);
+  const int grid = grid_for(ctx, a.nitems, occ, fcm ? 1 : ts.nw);
   int t = 0;
   SolveState* hst = (SolveState*)pin;
   TRY(timing_begin(ctx));
   while (t < p->max_iter) {
     const int k = p->eps > 0.f ? std::min(kChunk, p->max_iter - t) : p->max_iter - t;
-    for (int i = 0; i < k; ++i) HIPCHK(launch_step(C, a, grid, ts.ty, m2, fcm, true, ctx->s));
+    for (int i = 0; i < k; ++i) HIPCHK(launch_step(C, a, grid, ts.nw, m2, fcm, true, ctx->s));
     t += k;
     if (p->eps > 0.f && t < p->max_iter) {
       HIPCHK(hipMemcpyAsync(hst, st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, ctx->s));
@@ -465,8 +482,9 @@ pifcm_status solve_impl(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_par
   TRY(timing_end(ctx));
   // Objective of the final state (the fitness).
   LaunchArgs ae = a;
-  const int occe = fcm ? fcm_occupancy(C, m2, false) : gather_occupancy(C, ts.ty, m2, false);
-  HIPCHK(launch_step(C, ae, grid_for(ctx, a.nitems, occe), ts.ty, m2, fcm, false, ctx->s));
+  const int occe = fcm ? fcm_occupancy(C, m2, false) : gather_occupancy(C, ts.nw, m2, false);
+  HIPCHK(launch_step(C, ae, grid_for(ctx, a.nitems, occe, fcm ? 1 : ts.nw), ts.nw, m2, fcm, false,
+                     ctx->s));
   HIPCHK(hipMemcpyAsync(hst, st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, ctx->s));
   HIPCHK(hipStreamSynchronize(ctx->s));
   const int T = hst->iter;
@@ -592,7 +610,7 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
   std::vector<size_t> uoff(B), soff(B);
   for (int b = 0; b < B; ++b) {
     TileShape ts = shape_for(ctx, C, m2, vols[b]);
-    ts.ty = ts0.ty;
+    ts.nw = ts0.nw;
     vh[b] = make_vol(vols[b], (const float*)ctx->invg.p + off[b], ts);
     uoff[b] = ubytes;
     ubytes += (size_t)P * 2 * ((nvox(vols[b]) * C + 63) / 64 * 64) * sizeof(float);
@@ -637,8 +655,9 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
   for (long k = 0; k < 2L * B * P; ++k) fcm = fcm && particles[k] == 0.0f;
   const VolDev* vdev = (const VolDev*)ctx->tvol.p;
   const PairDev* pdev = (const PairDev*)ctx->tpair.p;
-  const int occ = fcm ? fcm_occupancy(C, m2, true) : gather_occupancy(C, ts0.ty, m2, true);
-  const int occe = fcm ? fcm_occupancy(C, m2, false) : gather_occupancy(C, ts0.ty, m2, false);
+  const int occ = fcm ? fcm_occupancy(C, m2, true) : gather_occupancy(C, ts0.nw, m2, true);
+  const int occe = fcm ? fcm_occupancy(C, m2, false) : gather_occupancy(C, ts0.nw, m2, false);
+  const int ipg = fcm ? 1 : ts0.nw;  // items in flight per work group
 
   int64_t launches = 0;
   auto all_stopped = [&](bool& done) -> pifcm_status {
@@ -651,12 +670,12 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
 
   if (mode == PIFCM_SWARM_BATCHED) {
     LaunchArgs a = make_args(vdev, pdev, vh, B, P, fcm, p);
-    const int grid = grid_for(ctx, a.nitems, occ);
+    const int grid = grid_for(ctx, a.nitems, occ, ipg);
     const int chunk = p->eps > 0.f ? std::min(kChunk, std::max(1, p->max_iter)) : std::max(1, p->max_iter);
     // Capture `chunk` fused launches once; replay until every pair stops.
     std::vector<char> key(sizeof(LaunchArgs) + 5 * sizeof(int));
     std::memcpy(key.data(), &a, sizeof a);
-    const int extra[5] = {grid, ts0.ty, C * 2 + (int)m2, (int)fcm, chunk};
+    const int extra[5] = {grid, ts0.nw, C * 2 + (int)m2, (int)fcm, chunk};
     std::memcpy(key.data() + sizeof a, extra, sizeof extra);
     if (ctx->graph.key != key || !ctx->graph.exec) {
       if (ctx->graph.exec) HIPCHK(hipGraphExecDestroy(ctx->graph.exec));
@@ -666,7 +685,7 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
       ctx->graph.key.clear();
       HIPCHK(hipStreamBeginCapture(ctx->s, hipStreamCaptureModeThreadLocal));
       for (int i = 0; i < chunk; ++i) {
-        hipError_t e = launch_step(C, a, grid, ts0.ty, m2, fcm, true, ctx->s);
+        hipError_t e = launch_step(C, a, grid, ts0.nw, m2, fcm, true, ctx->s);
         if (e != hipSuccess) {
           hipGraph_t g = nullptr;
           (void)hipStreamEndCapture(ctx->s, &g);
@@ -691,7 +710,7 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
     }
     TRY(timing_end(ctx));
     launches = t;
-    HIPCHK(launch_step(C, a, grid_for(ctx, a.nitems, occe), ts0.ty, m2, fcm, false, ctx->s));
+    HIPCHK(launch_step(C, a, grid_for(ctx, a.nitems, occe, ipg), ts0.nw, m2, fcm, false, ctx->s));
   } else {
     // One launch per (volume, particle) per iteration.
     std::vector<LaunchArgs> args(npairs);
@@ -701,8 +720,8 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
       for (int q = 0; q < P; ++q) {
         const size_t k = (size_t)b * P + q;
         args[k] = make_args(vdev + b, pdev + k, one, 1, 1, fcm, p);
-        grids[k] = grid_for(ctx, args[k].nitems, occ);
-        gride[k] = grid_for(ctx, args[k].nitems, occe);
+        grids[k] = grid_for(ctx, args[k].nitems, occ, ipg);
+        gride[k] = grid_for(ctx, args[k].nitems, occe, ipg);
       }
     }
     int t = 0;
@@ -711,7 +730,7 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
       const int k = p->eps > 0.f ? std::min(kChunk, p->max_iter - t) : p->max_iter - t;
       for (int i = 0; i < k; ++i)
         for (size_t q = 0; q < npairs; ++q)
-          HIPCHK(launch_step(C, args[q], grids[q], ts0.ty, m2, fcm, true, ctx->s));
+          HIPCHK(launch_step(C, args[q], grids[q], ts0.nw, m2, fcm, true, ctx->s));
       t += k;
       if (t < p->max_iter) {
         bool done = false;
@@ -722,7 +741,7 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
     TRY(timing_end(ctx));
     launches = (int64_t)t * (int64_t)npairs;
     for (size_t q = 0; q < npairs; ++q)
-      HIPCHK(launch_step(C, args[q], gride[q], ts0.ty, m2, fcm, false, ctx->s));
+      HIPCHK(launch_step(C, args[q], gride[q], ts0.nw, m2, fcm, false, ctx->s));
   }
   HIPCHK(hipMemcpyAsync(hs, st_dev, npairs * sizeof(SolveState), hipMemcpyDeviceToHost, ctx->s));
   HIPCHK(hipStreamSynchronize(ctx->s));

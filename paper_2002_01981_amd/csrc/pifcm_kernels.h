@@ -11,6 +11,9 @@ namespace pifcm {
 // the tiles of a launch; ty = rows per tile (2, 4 or 8).
 hipError_t launch_gather(int C, const LaunchArgs& a, int grid, int ty, bool m2, bool step,
                          hipStream_t s);
+// Per-pair fp64 sum of the tile slots of the preceding step / objective
+// launch and the state update (one work group per pair).
+hipError_t launch_finalize(int C, const LaunchArgs& a, int npairs, bool step, hipStream_t s);
 // Pointwise FCM step / objective (lambda = xi = 0).
 hipError_t launch_fcm(int C, const LaunchArgs& a, int grid, bool m2, bool step, hipStream_t s);
 hipError_t launch_init_u(int C, const float* x, size_t N, const SolveState* st, float m, bool m2,

@@ -14,25 +14,25 @@ __global__ __launch_bounds__(256) void k_fcm_point(const LaunchArgs a) {
   constexpr int NT = 256;
   constexpr int NV = STEP ? 2 * C + 1 : 1;
   __shared__ float s_red[(NT / 64) * NV];
-  __shared__ double s_redd[(NT / 64) * NV];
-  __shared__ int s_flag;
-  int first, end, step;
-  item_range(a.nitems, first, end, step);
-  for (int it = first; it < end; it += step) {
+  const int per = (a.nitems + 7) >> 3;
+  const int xcd = blockIdx.x & 7;
+  const int it_end = min(a.nitems, (xcd + 1) * per);
+  for (int it = xcd * per + (blockIdx.x >> 3); it < it_end; it += gridDim.x >> 3) {
     const int b = vol_of_item(a, it);
-    const VolDev vd = a.vols[b];
+    const VolDev vd = ld_const(a.vols + b);
     const int r = it - a.item_begin[b];
     const int pidx = r / vd.tiles1d;
     const int tile = r - pidx * vd.tiles1d;
-    const PairDev pr = a.pairs[b * a.P + pidx];
-    SolveState* st = pr.st;
-    if (STEP && st->stop) continue;
-    const int t = STEP ? st->iter + 1 : st->iter;
-    const float* __restrict__ Uin = STEP ? u_in_of(pr, t) : u_state_of(pr, t);
-    float* __restrict__ Uout = STEP ? u_out_of(pr, t) : nullptr;
+    const PairDev pr = ld_const(a.pairs + b * a.P + pidx);
+    const SolveState* st = pr.st;
+    if (STEP && ld_const(&st->stop)) continue;
+    const int t = STEP ? ld_const(&st->iter) + 1 : ld_const(&st->iter);
+    const gfloat* Uin = as_global(STEP ? u_in_of(pr, t) : u_state_of(pr, t));
+    gfloat* Uout = STEP ? as_global(u_out_of(pr, t)) : nullptr;
+    const gfloat* X = as_global(vd.x);
     float cj[C];
 #pragma unroll
-    for (int j = 0; j < C; ++j) cj[j] = st->c[(STEP ? t - 1 : t) & 1][j];
+    for (int j = 0; j < C; ++j) cj[j] = ld_const(&st->c[(STEP ? t - 1 : t) & 1][j]);
     const size_t N = (size_t)vd.nx * vd.ny * vd.nz;
     float acc[NV];
 #pragma unroll
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void k_fcm_point(const LaunchArgs a) {
     for (int k = 0; k < kFcmVoxPerThread; ++k) {
       const size_t i = base + (size_t)k * NT + threadIdx.x;
       if (i >= N) break;
-      const float xv = vd.x[i];
+      const float xv = X[i];
       float uo[C], d2[C];
       load_row<C>(Uin + i * C, uo);
       float Jv = 0.f;
@@ -67,14 +67,16 @@ __global__ __launch_bounds__(256) void k_fcm_point(const LaunchArgs a) {
         acc[0] += Jv;
       }
     }
-    tile_done<C, NT, STEP>(pr, tile, vd.tiles1d, acc, s_red, s_redd, &s_flag);
+    block_tile_store<NV, NT>(pr, tile, acc, s_red);
   }
 }
 
 // ----------------------------------------------------------- small kernels
-// Iteration invariants of one volume: 1 / sum_k |x_i - x_k| over the in-volume
-// 3x3x3 neighbourhood (denominator of eq (5)), -1 where every neighbour has
-// the voxel's intensity; also flags non-finite intensities.
+// Iteration invariants of one volume: g_inv = 1 / sum_k |x_i - x_k| over the
+// in-volume 3x3x3 neighbourhood (denominator of eq (5)); for a voxel whose
+// neighbours all have its intensity, -1 / (number of neighbours), which the
+// fused step turns into the equal-weight mean; 0 for a voxel without
+// neighbours.  Also flags non-finite intensities.
 __global__ __launch_bounds__(256) void k_invariants(const float* __restrict__ x, float* __restrict__ invg,
                                                     int nx, int ny, int nz, int* __restrict__ flag) {
   const size_t N = (size_t)nx * ny * nz;
@@ -87,6 +89,7 @@ __global__ __launch_bounds__(256) void k_invariants(const float* __restrict__ x,
     const float xi = x[i];
     if (!isfinite(xi)) atomicOr(flag, 1);
     float gsum = 0.f;
+    int cnt = 0;
     for (int dz = -1; dz <= 1; ++dz)
       for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
@@ -94,8 +97,9 @@ __global__ __launch_bounds__(256) void k_invariants(const float* __restrict__ x,
           if ((dx | dy | dz) == 0 || X2 < 0 || X2 >= nx || Y2 < 0 || Y2 >= ny || Z2 < 0 || Z2 >= nz)
             continue;
           gsum += fabsf(xi - x[((size_t)Z2 * ny + Y2) * nx + X2]);
+          ++cnt;
         }
-    invg[i] = gsum > 0.f ? 1.f / gsum : -1.f;
+    invg[i] = gsum > 0.f ? 1.f / gsum : (cnt > 0 ? -1.f / (float)cnt : 0.f);
   }
 }
 
@@ -117,7 +121,7 @@ __global__ __launch_bounds__(256) void k_init_u(const float* __restrict__ x, siz
       d2[j] = fmaxf(dd * dd, kDFloor);
     }
     memberships<C, M2>(d2, m, u);
-    store_row<C>(U + i * C, u);
+    store_row<C>(as_global(U) + i * C, u);
   }
 }
 
@@ -224,6 +228,13 @@ static hipError_t launch_fcm_c(const LaunchArgs& a, int grid, bool m2, bool step
 }
 
 template <int C>
+static hipError_t launch_finalize_c(const LaunchArgs& a, int npairs, bool step, hipStream_t s) {
+  if (step) hipLaunchKernelGGL((k_finalize<C, true>), dim3(npairs), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_finalize<C, false>), dim3(npairs), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int C>
 static hipError_t launch_init_c(const float* x, size_t N, const SolveState* st, float m, bool m2,
                                 float* U, hipStream_t s) {
   const int grid = (int)std::min<size_t>((N + 255) / 256, 65536);
@@ -267,6 +278,16 @@ hipError_t launch_fcm(int C, const LaunchArgs& a, int grid, bool m2, bool step, 
   switch (C) {
 #define CASE(c) \
   case c: return launch_fcm_c<c>(a, grid, m2, step, s);
+    PIFCM_FOR_EACH_C(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_finalize(int C, const LaunchArgs& a, int npairs, bool step, hipStream_t s) {
+  switch (C) {
+#define CASE(c) \
+  case c: return launch_finalize_c<c>(a, npairs, step, s);
     PIFCM_FOR_EACH_C(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
