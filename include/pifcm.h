@@ -100,6 +100,8 @@ pifcm_status pifcm_normalize(pifcm_ctx* ctx, const float* raw, int64_t n, float*
  * NULL: J of the input state of each iteration performed).
  * The squared distance of eq (4) is floored at 1e-12 so eq (2) stays
  * defined when the attraction factor is <= 0 or a voxel equals a centre.
+ * lambda and xi may lie outside [0, 1] but must satisfy |.| <= 1000
+ * (PIFCM_E_INVALID otherwise).
  * PIFCM_E_UNSUPPORTED for V > 1. */
 pifcm_status ifcm_solve(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
                         float lambda, float xi, const float* centres_in, const float* U_in,

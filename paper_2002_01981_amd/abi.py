@@ -15,7 +15,8 @@ from dataclasses import dataclass
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libpifcm.so")
+# PIFCM_LIB selects another build of the library (kernel variants).
+LIB_PATH = os.environ.get("PIFCM_LIB") or os.path.join(PKG, "libpifcm.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "pifcm.h")
 
 PIFCM_OK = 0

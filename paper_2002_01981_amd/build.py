@@ -28,17 +28,18 @@ HIPFLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 SOURCES = ["gather_c4.hip", "gather_c2_6.hip", "gather_c7_10.hip", "gather_c11_13.hip",
-           "gather_c14_16.hip", "pointwise.hip", "pifcm_host.cpp"]
+           "gather_c14_16.hip", "pointwise.hip", "adjoint.hip", "pifcm_host.cpp"]
 
 
 def _hipcc():
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
-def _compile(src: str, verbose: bool):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+def _compile(src: str, verbose: bool, build_dir: str, defines):
+    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [_hipcc(), *HIPFLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc(), *HIPFLAGS, *[f"-D{d}" for d in defines], *lang, "-c",
+           os.path.join(CSRC, src), "-o", obj]
     t0 = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)
     msgs = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
@@ -52,22 +53,31 @@ def _compile(src: str, verbose: bool):
     return obj
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, jobs: int | None = None, out: str = LIB,
+          build_dir: str = BUILD, defines=()) -> str:
+    """Compile every source and link `out`.  `defines` are extra -D macros
+    (kernel variants for experiments); `out`/`build_dir` place the result."""
+    os.makedirs(build_dir, exist_ok=True)
     jobs = jobs or min(len(SOURCES), max(1, os.cpu_count() or 1), 8)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, verbose, build_dir, defines), SOURCES))
+    tmp = out + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=LIB)
+    ap.add_argument("--build-dir", default=BUILD)
+    ap.add_argument("-D", dest="defines", action="append", default=[])
+    args = ap.parse_args()
     t = time.time()
-    build(verbose=True)
-    print(f"built {LIB} in {time.time() - t:.1f}s")
+    path = build(verbose=True, out=args.out, build_dir=args.build_dir, defines=args.defines)
+    print(f"built {path} in {time.time() - t:.1f}s")
     sys.exit(0)

@@ -13,6 +13,15 @@ typedef __attribute__((address_space(1))) float gfloat;
 __device__ __forceinline__ const gfloat* as_global(const float* p) { return (const gfloat*)p; }
 __device__ __forceinline__ gfloat* as_global(float* p) { return (gfloat*)p; }
 
+// base + a 32-bit byte offset: with a uniform base this is the scalar-base
+// plus vector-offset form of the global instructions (no 64-bit address math).
+__device__ __forceinline__ const gfloat* at_byte(const gfloat* base, uint32_t off) {
+  return (const gfloat*)((const __attribute__((address_space(1))) char*)base + off);
+}
+__device__ __forceinline__ gfloat* at_byte(gfloat* base, uint32_t off) {
+  return (gfloat*)((__attribute__((address_space(1))) char*)base + off);
+}
+
 // Read-only descriptor data (tables, particle state) through the constant
 // address space: uniform reads become scalar loads.
 template <typename T>
@@ -131,7 +140,32 @@ __device__ __forceinline__ float pow_m(float u, float m) {
 // (d2_min / d2_j)^(1/(m-1)), which is eq (2) scaled so no term overflows.
 template <int C, bool M2>
 __device__ __forceinline__ void memberships(const float (&d2)[C], float m, float (&u)[C]) {
-  if constexpr (M2) {
+  if constexpr (M2 && C <= 4) {
+    // u_j = P_j / sum_k P_k with P_j the product of the other d2: one
+    // reciprocal.  d2 lies in [1e-12, 2e3] (|lambda|, |xi| <= 1e3), so the
+    // products of at most three stay within float32's normal range.
+    float P[C];
+    if constexpr (C == 2) {
+      P[0] = d2[1];
+      P[1] = d2[0];
+    } else if constexpr (C == 3) {
+      P[0] = d2[1] * d2[2];
+      P[1] = d2[0] * d2[2];
+      P[2] = d2[0] * d2[1];
+    } else {
+      const float d01 = d2[0] * d2[1], d23 = d2[2] * d2[3];
+      P[0] = d2[1] * d23;
+      P[1] = d2[0] * d23;
+      P[2] = d2[3] * d01;
+      P[3] = d2[2] * d01;
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int j = 0; j < C; ++j) s += P[j];
+    const float r = frcp(s);
+#pragma unroll
+    for (int j = 0; j < C; ++j) u[j] = P[j] * r;
+  } else if constexpr (M2) {
     float s = 0.f;
 #pragma unroll
     for (int j = 0; j < C; ++j) {
@@ -222,6 +256,10 @@ __device__ __forceinline__ void finish_pair(SolveState* st, const double* tot) {
       const double den = tot[C + j];
       st->c[par][j] = den > 0.0 ? (float)(tot[j] / den) : st->c[par ^ 1][j];
     }
+    if (st->B_hist)
+      for (int j = 0; j < C; ++j) st->B_hist[(size_t)(t - 1) * C + j] = tot[C + j];
+    if (st->c_hist)
+      for (int j = 0; j < C; ++j) st->c_hist[(size_t)t * C + j] = st->c[par][j];
     const double J = tot[2 * C];
     if (st->J_hist) st->J_hist[t - 1] = J;
     int stop = 0;

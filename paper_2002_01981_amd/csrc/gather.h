@@ -64,8 +64,10 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
   constexpr int CH = C - 1;  // clusters whose H is gathered
   constexpr int NV = STEP ? 2 * C + 1 : 1;
 
-  __shared__ float s_x[NW][2][kNCell];
-  __shared__ __align__(16) float s_u[NW][2][kNCell * CP];
+  // Three plane buffers per wave: the plane being read, the one before it
+  // (own cells of the voxel being finalised), and the one being staged.
+  __shared__ float s_x[NW][3][kNCell];
+  __shared__ __align__(16) float s_u[NW][3][kNCell * CP];
 
   const int lane = threadIdx.x & 63;
   // The wave index is uniform across the wave; say so, so that every value
@@ -82,9 +84,11 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
   const bool hlane = lane < kNHalo;
   const int halo_cell = hlane ? hcy * kHX + hcx : 0;
   // eq (7) weights by offset class: in-plane edge / corner (q = 1, 2) and
-  // off-plane centre / edge / corner (q = 1, 2, 3); q^2 or q.
-  const float wEa = 1.f, wCa = a.q2_sqdist ? 2.f : 4.f;
-  const float wPb = 1.f, wEb = a.q2_sqdist ? 2.f : 4.f, wCb = a.q2_sqdist ? 3.f : 9.f;
+  // off-plane centre / edge / corner (q = 1, 2, 3); q^2 or q.  The weight
+  // of q = 1 is 1 in both readings.
+  constexpr float wEa = 1.f, wPb = 1.f;
+  const float wCa = a.q2_sqdist ? 2.f : 4.f;
+  const float wEb = a.q2_sqdist ? 2.f : 4.f, wCb = a.q2_sqdist ? 3.f : 9.f;
 
   // Items: 8 contiguous ranges, one per XCD (work groups go to the XCDs
   // round-robin), walked by that XCD's waves so neighbouring tiles share L2.
@@ -134,17 +138,29 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
     // Denominator of eq (7): in-plane edges e and corners e_x * e_y, plus for
     // each of the az existing off-planes a centre, e edges and e_x * e_y
     // corners.
-    float invQ[3];
+    float invQ0, invQ1, invQ2;  // by the number of existing off-planes
     {
       const int ex = (gx > 0) + (gx < nx - 1), ey = (gy > 0) + (gy < ny - 1);
       const float e = (float)(ex + ey), co = (float)(ex * ey);
       const float q0 = wEa * e + wCa * co, q1 = wPb + wEb * e + wCb * co;
-#pragma unroll
-      for (int az = 0; az < 3; ++az) {
-        const float q = q0 + (float)az * q1;
-        invQ[az] = q > 0.f ? 1.f / q : 0.f;
-      }
+      invQ0 = q0 > 0.f ? 1.f / q0 : 0.f;
+      invQ1 = 1.f / (q0 + q1);
+      invQ2 = 1.f / (q0 + 2.f * q1);
     }
+
+    // Plane q lives in buffer (q - zlo + 1) % 3: the tile's first staged
+    // plane (zlo - 1) in buffer 0.  In the unrolled interior loop the buffer of
+    // every access is a compile-time constant, so LDS addresses are one lane
+    // base plus immediate offsets.
+    float* const sxw = &s_x[wave][0][0] + own_cell;
+    float* const suw = &s_u[wave][0][0] + own_cell * CP;
+    auto bufof = [&](int q) { return (q - zlo + 1) % 3; };
+    auto sx_at = [&](int buf, int dy, int dx) -> float {
+      return sxw[buf * kNCell + dy * kHX + dx];
+    };
+    auto su_at = [&](int buf, int dy, int dx, float (&u)[C]) {
+      lds_cell_load<C, CP>(suw + (buf * kNCell + dy * kHX + dx) * CP, u);
+    };
 
     // Prefetch registers of the next plane.
     float rx, rg, ru[C], rhx, rhu[C];
@@ -152,10 +168,10 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
       const bool pv = q >= 0 && q < nz;
       const uint32_t pofs = (uint32_t)(q - zb) * psz;
       if (pv && active) {
-        const uint32_t o = pofs + own_xy;
-        rx = Xb[o];
-        rg = Gb[o];
-        load_row<C>(Ub + o * C, ru);
+        const uint32_t ob = (pofs + own_xy) * 4u;
+        rx = *at_byte(Xb, ob);
+        rg = *at_byte(Gb, ob);
+        load_row<C>(at_byte(Ub, ob * C), ru);
       } else {
         rx = 0.f;
         rg = 1.f;
@@ -163,9 +179,9 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
         for (int j = 0; j < C; ++j) ru[j] = 0.f;
       }
       if (pv && hvalid) {
-        const uint32_t o = pofs + halo_xy;
-        rhx = Xb[o];
-        load_row<C>(Ub + o * C, rhu);
+        const uint32_t ob = (pofs + halo_xy) * 4u;
+        rhx = *at_byte(Xb, ob);
+        load_row<C>(at_byte(Ub, ob * C), rhu);
       } else {
         rhx = 0.f;
 #pragma unroll
@@ -173,8 +189,8 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
       }
     };
     auto store_plane = [&](int buf) __attribute__((always_inline)) {
-      float* sx = s_x[wave][buf];
-      float* su = s_u[wave][buf];
+      float* sx = &s_x[wave][buf][0];
+      float* su = &s_u[wave][buf][0];
       sx[own_cell] = rx;
       lds_cell_store<C, CP>(su + own_cell * CP, ru);
       if (hlane) {
@@ -184,36 +200,37 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
     };
 
     // Slots of the three voxels in flight: gathered H numerators, F class
-    // sums, centre value for g (xs), intensity (xt), |g_inv| (gs), input
-    // memberships (us).
-    float hn[3][CH], fn[3][C], xs[3], xt[3], gs[3], us[3][C];
+    // sums and the stored g_inv (its sign marks a flat neighbourhood).
+    float hn[3][CH], fn[3][C], gs[3];
     float acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.f;
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      xs[s] = xt[s] = 0.f;
-      gs[s] = 0.f;
+    for (int s2 = 0; s2 < 3; ++s2) {
+      gs[s2] = 1.f;
 #pragma unroll
-      for (int j = 0; j < CH; ++j) hn[s][j] = 0.f;
+      for (int j = 0; j < CH; ++j) hn[s2][j] = 0.f;
 #pragma unroll
-      for (int j = 0; j < C; ++j) fn[s][j] = us[s][j] = 0.f;
+      for (int j = 0; j < C; ++j) fn[s2][j] = 0.f;
     }
 
-    // Finalise voxel z held in slot S: eqs (5)/(7) ratios, (4), (1), (2), (3).
-    auto finalize = [&](int z, auto Sc) __attribute__((always_inline)) {
+    // Finalise voxel z of slot S; its own cell is in buffer bz:
+    // eqs (5)/(7) ratios, (4), (1), (2), (3).
+    auto finalize = [&](int z, auto Sc, int bz) __attribute__((always_inline)) {
       constexpr int S = decltype(Sc)::value;
       if (!active) return;
-      const float iq = invQ[(z > 0) + (z < nz - 1)];
-      const float ig = gs[S];
-      // a_j = 1 - lambda H_j - xi F_j with H_j = hn_j * ig, F_j = fn_j * iq.
-      const float lg = -lam * ig, xq = -xi * iq;
+      const float xv = sx_at(bz, 0, 0);
+      float uo[C];
+      su_at(bz, 0, 0, uo);
+      const float iq = (z > 0 && z < nz - 1) ? invQ2 : ((z > 0 || z < nz - 1) ? invQ1 : invQ0);
+      const float g = fabsf(gs[S]);
+      // a_j = 1 - lambda H_j - xi F_j with H_j = hn_j * g, F_j = fn_j * iq.
+      const float lg = -lam * g, xq = -xi * iq;
       float sh = 0.f;
 #pragma unroll
       for (int j = 0; j < CH; ++j) sh += hn[S][j];
       // Last cluster by sum_j H_ij = 1 (0 when the voxel has no neighbour).
-      const float hlast = ig != 0.f ? fmaf(-ig, sh, 1.f) : 0.f;
-      const float xv = xt[S];
+      const float hlast = g != 0.f ? fmaf(-g, sh, 1.f) : 0.f;
       float d2[C];
       float Jv = 0.f;
 #pragma unroll
@@ -222,13 +239,13 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
         const float av = fmaf(xq, fn[S][j], ah);  // eq (4) factor
         const float dd = xv - cj[j];
         d2[j] = fmaxf(dd * dd * av, kDFloor);
-        Jv = fmaf(pow_m<M2>(us[S][j], a.m), d2[j], Jv);  // eq (1)
+        Jv = fmaf(pow_m<M2>(uo[j], a.m), d2[j], Jv);  // eq (1)
       }
       if constexpr (STEP) {
         float un[C];
         memberships<C, M2>(d2, a.m, un);  // eq (2)
-        const uint32_t o = (uint32_t)(z - zb) * psz + own_xy;
-        store_row<C>(Ob + o * C, un);
+        const uint32_t ob = ((uint32_t)(z - zb) * psz + own_xy) * (4u * C);
+        store_row<C>(at_byte(Ob, ob), un);
 #pragma unroll
         for (int j = 0; j < C; ++j) {
           const float w = pow_m<M2>(un[j], a.m);
@@ -243,11 +260,16 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
 
     // One plane p: contributions of its 3x3 cells to voxels p-1 (slot SA),
     // p (SB) and p+1 (SC); finalise p-1; stage plane p+1; prefetch p+2.
-    // GEN: the tile's first / last planes, with the validity tests.
-    auto plane = [&](int p, auto SAc, auto SBc, auto SCc, auto GENc) __attribute__((always_inline)) {
+    // BP: buffer of plane p (-1: computed at run time); GEN: the tile's
+    // first / last planes, with the validity tests.
+    auto plane = [&](int p, auto SAc, auto SBc, auto SCc, auto BPc, auto GENc) __attribute__((always_inline)) {
       constexpr int SA = decltype(SAc)::value, SB = decltype(SBc)::value;
       constexpr int SC = decltype(SCc)::value;
+      constexpr int BPS = decltype(BPc)::value;
       constexpr bool GEN = decltype(GENc)::value;
+      const int bp = BPS >= 0 ? BPS : bufof(p);
+      const int bprev = BPS >= 0 ? (BPS + 2) % 3 : bufof(p + 2);  // plane p-1
+      const int bnext = BPS >= 0 ? (BPS + 1) % 3 : bufof(p + 1);  // plane p+1
       const bool pv = !GEN || (p >= 0 && p < nz);
       const bool doA = !GEN || p - 1 >= zlo;
       const bool doB = !GEN || (p >= zlo && p < zhi);
@@ -256,26 +278,29 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
 #ifdef PIFCM_PLANE_SCHED_FENCE
       __builtin_amdgcn_sched_barrier(0);
 #endif
-      // Centre value of voxel p+1 (from the prefetched plane).
-      const float xC = rg < 0.f ? rx - 1.f : rx;
+      // Centre values for g (shifted by -1 for a flat neighbourhood).
+      const float xA = doA ? sx_at(bprev, 0, 0) : 0.f;
+      const float xcA = gs[SA] < 0.f ? xA - 1.f : xA;
+      const float xC = rg < 0.f ? rx - 1.f : rx;  // voxel p+1, prefetched
       if (pv) {
-        const float* __restrict__ sx = s_x[wave][p & 1];
-        const float* __restrict__ su = s_u[wave][p & 1];
         float E[C], Co[C], Pc[C];
-        float hA[CH], hB[CH], hC[CH];
+        // H gathers accumulate straight into the slots of voxels p-1 and p.
+        float hC[CH];
 #pragma unroll
         for (int j = 0; j < C; ++j) E[j] = Co[j] = Pc[j] = 0.f;
 #pragma unroll
-        for (int j = 0; j < CH; ++j) hA[j] = hB[j] = hC[j] = 0.f;
-        const float xA = xs[SA], xB = xs[SB];
+        for (int j = 0; j < CH; ++j) hC[j] = 0.f;
+        float (&hA)[CH] = hn[SA];
+        float (&hB)[CH] = hn[SB];
+        const float xB = sx_at(bp, 0, 0);
+        const float xcB = gs[SB] < 0.f ? xB - 1.f : xB;
 #pragma unroll
         for (int dy = -1; dy <= 1; ++dy) {
 #pragma unroll
           for (int dx = -1; dx <= 1; ++dx) {
-            const int cell = own_cell + dy * kHX + dx;
-            const float xk = sx[cell];
+            const float xk = sx_at(bp, dy, dx);
             float u[C];
-            lds_cell_load<C, CP>(su + cell * CP, u);
+            su_at(bp, dy, dx, u);
             const int n = (dx != 0) + (dy != 0);
 #pragma unroll
             for (int j = 0; j < C; ++j) {
@@ -284,12 +309,12 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
               else Co[j] = fmaf(u[j], u[j], Co[j]);
             }
             if (doA) {
-              const float g = fabsf(xA - xk);  // eq (6)
+              const float g = fabsf(xcA - xk);  // eq (6)
 #pragma unroll
               for (int j = 0; j < CH; ++j) hA[j] = fmaf(u[j], g, hA[j]);
             }
             if (doB && n != 0) {
-              const float g = fabsf(xB - xk);
+              const float g = fabsf(xcB - xk);
 #pragma unroll
               for (int j = 0; j < CH; ++j) hB[j] = fmaf(u[j], g, hB[j]);
             }
@@ -308,13 +333,9 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
         }
         if (doA) {
 #pragma unroll
-          for (int j = 0; j < CH; ++j) hn[SA][j] += hA[j];
-#pragma unroll
           for (int j = 0; j < C; ++j) fn[SA][j] += Sb[j];
         }
         if (doB) {
-#pragma unroll
-          for (int j = 0; j < CH; ++j) hn[SB][j] += hB[j];
 #pragma unroll
           for (int j = 0; j < C; ++j) fn[SB][j] += Sa[j];
         }
@@ -330,14 +351,10 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
 #pragma unroll
         for (int j = 0; j < C; ++j) fn[SC][j] = 0.f;
       }
-      if (doA) finalize(p - 1, SAc);
+      if (doA) finalize(p - 1, SAc, bprev);
       if (!GEN || p + 1 <= zhi) {
-        store_plane((p + 1) & 1);
-        xs[SC] = xC;
-        xt[SC] = rx;
-        gs[SC] = fabsf(rg);
-#pragma unroll
-        for (int j = 0; j < C; ++j) us[SC][j] = ru[j];
+        store_plane(bnext);
+        gs[SC] = rg;
         if (!GEN || p + 2 <= zhi) load_plane(p + 2);
       }
     };
@@ -346,40 +363,38 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
     // processed with the canonical slots, move the ring down by one.
     auto shift = [&]() __attribute__((always_inline)) {
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        xs[s] = xs[s + 1];
-        xt[s] = xt[s + 1];
-        gs[s] = gs[s + 1];
+      for (int s2 = 0; s2 < 2; ++s2) {
+        gs[s2] = gs[s2 + 1];
 #pragma unroll
-        for (int j = 0; j < CH; ++j) hn[s][j] = hn[s + 1][j];
+        for (int j = 0; j < CH; ++j) hn[s2][j] = hn[s2 + 1][j];
 #pragma unroll
-        for (int j = 0; j < C; ++j) {
-          fn[s][j] = fn[s + 1][j];
-          us[s][j] = us[s + 1][j];
-        }
+        for (int j = 0; j < C; ++j) fn[s2][j] = fn[s2 + 1][j];
       }
     };
 
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
     using I2 = std::integral_constant<int, 2>;
+    using Bdyn = std::integral_constant<int, -1>;
     using Gen = std::integral_constant<bool, true>;
     using Steady = std::integral_constant<bool, false>;
 
-    // Prologue: stage plane zlo-1 (zeros outside the volume), prefetch zlo.
+    // Prologue: stage plane zlo-1 (zeros outside the volume) in buffer 0,
+    // prefetch zlo.
     load_plane(zlo - 1);
-    store_plane((zlo - 1) & 1);
+    store_plane(0);
     load_plane(zlo);
     int p = zlo - 1;
     while (p <= zhi) {
       if (p > zlo && p + 4 <= zhi) {
-        // Three interior planes: every test is true; slots rotate by name.
-        plane(p, I0{}, I1{}, I2{}, Steady{});
-        plane(p + 1, I1{}, I2{}, I0{}, Steady{});
-        plane(p + 2, I2{}, I0{}, I1{}, Steady{});
+        // Three interior planes (always entered at p = zlo + 1 + 3k, whose
+        // plane sits in buffer 2): every test is true, slots rotate by name.
+        plane(p, I0{}, I1{}, I2{}, I2{}, Steady{});
+        plane(p + 1, I1{}, I2{}, I0{}, I0{}, Steady{});
+        plane(p + 2, I2{}, I0{}, I1{}, I1{}, Steady{});
         p += 3;
       } else {
-        plane(p, I0{}, I1{}, I2{}, Gen{});
+        plane(p, I0{}, I1{}, I2{}, Bdyn{}, Gen{});
         shift();
         p += 1;
       }

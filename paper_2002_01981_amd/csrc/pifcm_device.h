@@ -27,6 +27,10 @@ struct alignas(64) SolveState {
   double J_prev2;      // J(t-2)
   double J_eval;       // J of the final state (fitness)
   double* J_hist;      // optional device [max_iter]: J(t-1) of iteration t
+  double* B_hist;      // optional device [max_iter][C]: eq (3) denominators
+                       // sum_i u_ij^m of iteration t's new memberships
+  float* c_hist;       // optional device [max_iter + 1][C]: c^(t) after
+                       // iteration t (row 0 is set by the host)
 };
 
 // One volume of a launch.

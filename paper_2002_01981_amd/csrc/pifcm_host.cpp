@@ -40,6 +40,7 @@ struct TileShape {
 };
 
 constexpr int kChunk = 8;            // iterations between stop-flag reads
+constexpr float kMaxWeight = 1000.f; // |lambda|, |xi| accepted
 constexpr int kMaxPairs = 65536;
 
 }  // namespace
@@ -52,6 +53,7 @@ struct pifcm_ctx {
   std::string err;
   int num_cu = 256;
   DevBuf invg, ubuf, partials, states, jhist, tvol, tpair, flags;
+  DevBuf adj_ck, adj_seg, adj_bar, adj_pq, adj_misc;  // ifcm_backward workspace
   void* pinned = nullptr;
   size_t pinned_cap = 0;
   GraphCache graph;
@@ -352,7 +354,8 @@ void pifcm_destroy(pifcm_ctx* ctx) {
   if (ctx->graph.exec) (void)hipGraphExecDestroy(ctx->graph.exec);
   if (ctx->graph.graph) (void)hipGraphDestroy(ctx->graph.graph);
   for (DevBuf* b : {&ctx->invg, &ctx->ubuf, &ctx->partials, &ctx->states, &ctx->jhist, &ctx->tvol,
-                    &ctx->tpair, &ctx->flags})
+                    &ctx->tpair, &ctx->flags, &ctx->adj_ck, &ctx->adj_seg, &ctx->adj_bar,
+                    &ctx->adj_pq, &ctx->adj_misc})
     if (b->p) (void)hipFree(b->p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
@@ -509,8 +512,8 @@ pifcm_status check_solve_args(pifcm_ctx* ctx, const pifcm_volume* vol, const pif
                               const float* U_out) {
   TRY(check_volume(ctx, vol));
   TRY(check_params(ctx, p));
-  if (!std::isfinite(lambda) || !std::isfinite(xi))
-    return fail(ctx, PIFCM_E_INVALID, "lambda and xi must be finite");
+  if (!(std::fabs(lambda) <= kMaxWeight) || !(std::fabs(xi) <= kMaxWeight))
+    return fail(ctx, PIFCM_E_INVALID, "lambda and xi must be finite with magnitude <= %g", kMaxWeight);
   if (!centres_in) return fail(ctx, PIFCM_E_INVALID, "centres_in is NULL");
   for (int j = 0; j < p->C; ++j)
     if (!std::isfinite(centres_in[j])) return fail(ctx, PIFCM_E_INVALID, "centres_in[%d] is not finite", j);
@@ -598,7 +601,8 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
       if (!std::isfinite(centres0[b * C + j])) return fail(ctx, PIFCM_E_INVALID, "centres0[%d][%d] is not finite", b, j);
   }
   for (long k = 0; k < 2L * B * P; ++k)
-    if (!std::isfinite(particles[k])) return fail(ctx, PIFCM_E_INVALID, "particle value %ld is not finite", k);
+    if (!(std::fabs(particles[k]) <= kMaxWeight))
+      return fail(ctx, PIFCM_E_INVALID, "particle value %ld is not finite or exceeds %g", k, kMaxWeight);
   TRY(begin(ctx));
   std::vector<size_t> off;
   TRY(prepare_volumes(ctx, vols, B, C, U0, off));
@@ -763,9 +767,179 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
                            double* dJ_dxi, double* dJ_dcentres) {
   if (!ctx) return PIFCM_E_INVALID;
   ctx->err.clear();
-  (void)vol; (void)p; (void)lambda; (void)xi; (void)centres0; (void)U0; (void)K;
-  (void)ckpt_every; (void)J_out; (void)dJ_dlambda; (void)dJ_dxi; (void)dJ_dcentres;
-  return fail(ctx, PIFCM_E_UNSUPPORTED, "ifcm_backward is not built yet");
+  TRY(check_volume(ctx, vol));
+  TRY(check_params(ctx, p));
+  if (!(std::fabs(lambda) <= kMaxWeight) || !(std::fabs(xi) <= kMaxWeight))
+    return fail(ctx, PIFCM_E_INVALID, "lambda and xi must be finite with magnitude <= %g", kMaxWeight);
+  if (!centres0 || !U0 || !dJ_dlambda || !dJ_dxi || !dJ_dcentres)
+    return fail(ctx, PIFCM_E_INVALID, "centres0, U0 and the gradient outputs must be non-NULL");
+  for (int j = 0; j < p->C; ++j)
+    if (!std::isfinite(centres0[j])) return fail(ctx, PIFCM_E_INVALID, "centres0[%d] is not finite", j);
+  if (!aligned16(U0)) return fail(ctx, PIFCM_E_INVALID, "U0 must be 16-byte aligned");
+  if (K < 1 || K > 100000) return fail(ctx, PIFCM_E_INVALID, "K = %d outside [1, 1e5]", K);
+  if (ckpt_every < 1 || ckpt_every > K)
+    return fail(ctx, PIFCM_E_INVALID, "ckpt_every = %d outside [1, K = %d]", ckpt_every, K);
+  const int C = p->C, S = ckpt_every;
+  const bool m2 = p->m == 2.0f;
+  const bool fcm = lambda == 0.0f && xi == 0.0f;
+  const size_t N = nvox(*vol);
+  const size_t UB = N * C * sizeof(float);
+  TRY(begin(ctx));
+  std::vector<size_t> off;
+  const float* u0s[1] = {U0};
+  TRY(prepare_volumes(ctx, vol, 1, C, u0s, off));
+  const TileShape ts = shape_for(ctx, C, m2, *vol);
+  std::vector<VolDev> vh{make_vol(*vol, (const float*)ctx->invg.p, ts)};
+  const int slots = std::max(vh[0].tiles, vh[0].tiles1d);
+  // Workspace: forward ping-pong, checkpoints at t = S, 2S, ... <= K - 1,
+  // the S - 1 recomputed states of a segment, two adjoint buffers, the
+  // transpose sources, slots and small histories.
+  const int nck = (K - 1) / S;
+  const size_t hist_doubles = (size_t)(K + 1) * C * 2 + (size_t)K + 2;
+  const size_t adj_slots = adjoint_slots(N) * (C + 2);
+  TRY(ensure(ctx, ctx->ubuf, 2 * UB, "memberships"));
+  TRY(ensure(ctx, ctx->adj_ck, (size_t)std::max(nck, 1) * UB, "checkpoints"));
+  TRY(ensure(ctx, ctx->adj_seg, (size_t)std::max(S - 1, 1) * UB, "segment states"));
+  TRY(ensure(ctx, ctx->adj_bar, 2 * UB, "adjoint memberships"));
+  TRY(ensure(ctx, ctx->adj_pq, 2 * UB, "transpose sources"));
+  TRY(ensure(ctx, ctx->adj_misc, adj_slots * sizeof(float) + hist_doubles * sizeof(double) +
+                                     (size_t)(K + 1) * C * sizeof(float) + 1024, "adjoint sums"));
+  TRY(ensure(ctx, ctx->partials, (size_t)slots * (2 * C + 1) * sizeof(float), "tile sums"));
+  TRY(ensure(ctx, ctx->states, 2 * sizeof(SolveState), "solve states"));
+  TRY(ensure(ctx, ctx->jhist, (size_t)K * sizeof(double), "objective history"));
+  const size_t pin_need = (size_t)(S + 2) * (sizeof(SolveState) + sizeof(PairDev)) + sizeof(VolDev) +
+                          (size_t)(K + 1) * C * sizeof(float) + 64 * sizeof(double) + 4096;
+  TRY(ensure_pinned(ctx, pin_need));
+  char* misc = (char*)ctx->adj_misc.p;
+  float* adj_parts = (float*)misc;
+  double* cbar = (double*)(misc + ((adj_slots * sizeof(float) + 255) / 256) * 256);
+  double* acc2 = cbar + (size_t)(K + 1) * C;
+  double* B_hist = acc2 + 2;
+  float* c_hist = (float*)(B_hist + (size_t)K * C);
+  float* ubA = (float*)ctx->ubuf.p;
+  float* ubB = (float*)((char*)ctx->ubuf.p + UB);
+  SolveState* st_dev = (SolveState*)ctx->states.p;
+  PairDev* tp = (PairDev*)ctx->tpair.p;
+  char* pin = (char*)ctx->pinned;
+
+  // ---------------------------------------------------------------- forward
+  pifcm_params pf = *p;
+  pf.eps = 0.f;
+  pf.max_iter = K;
+  SolveState hs = init_state(centres0, C, lambda, xi, &pf, (double*)ctx->jhist.p);
+  hs.B_hist = B_hist;
+  hs.c_hist = c_hist;
+  PairDev pr{};
+  pr.U0 = U0;
+  pr.Ua = ubA;
+  pr.Ub = ubB;
+  pr.st = st_dev;
+  pr.partials = (float*)ctx->partials.p;
+  std::memcpy(pin, &hs, sizeof hs);
+  std::memcpy(pin + sizeof(SolveState), &pr, sizeof pr);
+  std::memcpy(pin + sizeof(SolveState) + sizeof(PairDev), &vh[0], sizeof(VolDev));
+  std::memcpy(pin + sizeof(SolveState) + sizeof(PairDev) + sizeof(VolDev), centres0, C * sizeof(float));
+  HIPCHK(hipMemcpyAsync(st_dev, pin, sizeof hs, hipMemcpyHostToDevice, ctx->s));
+  HIPCHK(hipMemcpyAsync(tp, pin + sizeof(SolveState), sizeof pr, hipMemcpyHostToDevice, ctx->s));
+  HIPCHK(hipMemcpyAsync(ctx->tvol.p, pin + sizeof(SolveState) + sizeof(PairDev), sizeof(VolDev),
+                        hipMemcpyHostToDevice, ctx->s));
+  HIPCHK(hipMemcpyAsync(c_hist, pin + sizeof(SolveState) + sizeof(PairDev) + sizeof(VolDev),
+                        C * sizeof(float), hipMemcpyHostToDevice, ctx->s));
+  LaunchArgs a = make_args((const VolDev*)ctx->tvol.p, tp, vh, 1, 1, fcm, p);
+  const int occ = fcm ? fcm_occupancy(C, m2, true) : gather_occupancy(C, ts.nw, m2, true);
+  const int grid = grid_for(ctx, a.nitems, occ, fcm ? 1 : ts.nw);
+  const int occe = fcm ? fcm_occupancy(C, m2, false) : gather_occupancy(C, ts.nw, m2, false);
+  const int gride = grid_for(ctx, a.nitems, occe, fcm ? 1 : ts.nw);
+  auto ckpt = [&](int t) -> float* { return (float*)((char*)ctx->adj_ck.p + (size_t)(t / S - 1) * UB); };
+  for (int t = 0; t < K; ++t) {
+    HIPCHK(launch_step(C, a, grid, ts.nw, m2, fcm, true, ctx->s));
+    if ((t + 1) % S == 0 && t + 1 <= K - 1)
+      HIPCHK(hipMemcpyAsync(ckpt(t + 1), u_out_of(pr, t + 1), UB, hipMemcpyDeviceToDevice, ctx->s));
+  }
+  HIPCHK(launch_step(C, a, gride, ts.nw, m2, fcm, false, ctx->s));
+  SolveState* hst = (SolveState*)pin;
+  float* hc = (float*)(pin + (size_t)(S + 2) * (sizeof(SolveState) + sizeof(PairDev)) + sizeof(VolDev));
+  HIPCHK(hipMemcpyAsync(hst, st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, ctx->s));
+  HIPCHK(hipMemcpyAsync(hc, c_hist, (size_t)(K + 1) * C * sizeof(float), hipMemcpyDeviceToHost, ctx->s));
+  HIPCHK(hipStreamSynchronize(ctx->s));
+  const double J = hst->J_eval;
+  const float* UK = u_state_of(pr, K);
+  std::vector<float> chost(hc, hc + (size_t)(K + 1) * C);
+
+  // --------------------------------------------------------------- backward
+  HIPCHK(hipMemsetAsync(acc2, 0, 2 * sizeof(double), ctx->s));
+  float* bar0 = (float*)ctx->adj_bar.p;
+  float* bar1 = (float*)((char*)ctx->adj_bar.p + UB);
+  AdjArgs ad{};
+  ad.x = vol->x;
+  ad.invg = (const float*)ctx->invg.p;
+  ad.nx = vol->nx;
+  ad.ny = vol->ny;
+  ad.nz = vol->nz;
+  ad.q2_sqdist = (p->flags & PIFCM_Q2_SQDIST) ? 1 : 0;
+  ad.m = p->m;
+  ad.lam = lambda;
+  ad.xi = xi;
+  ad.PQ = (float*)ctx->adj_pq.p;
+  ad.partials = adj_parts;
+  // The objective at the final state.
+  ad.U = UK;
+  ad.c = c_hist + (size_t)K * C;
+  ad.Ubar_direct = bar1;
+  HIPCHK(launch_adjoint(C, ad, m2, true, bar0, cbar + (size_t)K * C, acc2, ctx->s));
+  float* cur = bar0;
+  float* other = bar1;
+  // Recomputed states of the current segment: seg[i] = U^(t0 + i).
+  std::vector<const float*> seg(S, nullptr);
+  int seg_t0 = -1;
+  LaunchArgs a1 = make_args((const VolDev*)ctx->tvol.p, tp + 1, vh, 1, 1, fcm, p);
+  for (int t = K - 1; t >= 0; --t) {
+    const int t0 = (t / S) * S;
+    if (t0 != seg_t0) {
+      seg[0] = t0 == 0 ? U0 : ckpt(t0);
+      const int len = std::min(S, K - t0);
+      for (int i = 1; i < len; ++i) {
+        // One forward iteration U^(t0+i-1) -> U^(t0+i) with c^(t0+i-1).
+        char* slot = pin + (size_t)(i + 1) * (sizeof(SolveState) + sizeof(PairDev));
+        pifcm_params p1 = *p;
+        p1.eps = 0.f;
+        p1.max_iter = 1;
+        SolveState s1 = init_state(&chost[(size_t)(t0 + i - 1) * C], C, lambda, xi, &p1, nullptr);
+        PairDev q{};
+        q.U0 = seg[i - 1];
+        q.Ua = (float*)((char*)ctx->adj_seg.p + (size_t)(i - 1) * UB);
+        q.Ub = q.Ua;
+        q.st = st_dev + 1;
+        q.partials = (float*)ctx->partials.p;
+        std::memcpy(slot, &s1, sizeof s1);
+        std::memcpy(slot + sizeof(SolveState), &q, sizeof q);
+        HIPCHK(hipMemcpyAsync(st_dev + 1, slot, sizeof s1, hipMemcpyHostToDevice, ctx->s));
+        HIPCHK(hipMemcpyAsync(tp + 1, slot + sizeof(SolveState), sizeof q, hipMemcpyHostToDevice, ctx->s));
+        HIPCHK(launch_step(C, a1, grid, ts.nw, m2, fcm, true, ctx->s));
+        seg[i] = q.Ua;
+      }
+      HIPCHK(hipStreamSynchronize(ctx->s));  // pinned slots are reused by the next segment
+      seg_t0 = t0;
+    }
+    ad.U = seg[t - t0];
+    ad.c = c_hist + (size_t)t * C;
+    ad.Ubar_next = cur;
+    ad.cbar_next = cbar + (size_t)(t + 1) * C;
+    ad.c_next = c_hist + (size_t)(t + 1) * C;
+    ad.B_next = B_hist + (size_t)t * C;
+    HIPCHK(launch_adjoint(C, ad, m2, false, t > 0 ? other : nullptr, cbar + (size_t)t * C, acc2, ctx->s));
+    std::swap(cur, other);
+  }
+  double* hout = (double*)(pin + pin_need - 64 * sizeof(double) - 4096);
+  HIPCHK(hipMemcpyAsync(hout, cbar, C * sizeof(double), hipMemcpyDeviceToHost, ctx->s));
+  HIPCHK(hipMemcpyAsync(hout + C, acc2, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->s));
+  HIPCHK(hipStreamSynchronize(ctx->s));
+  TRY(finish(ctx));
+  if (J_out) *J_out = J;
+  *dJ_dlambda = hout[C];
+  *dJ_dxi = hout[C + 1];
+  for (int j = 0; j < C; ++j) dJ_dcentres[j] = hout[j];
+  return PIFCM_OK;
 }
 
 pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, const pifcm_params* p,

@@ -28,6 +28,30 @@ hipError_t launch_permute(const float* U, size_t N, int C, const int32_t* perm, 
 // {0xffffffff, 0}) and a non-finite flag, then the scaling pass.
 hipError_t launch_minmax(const float* raw, size_t n, uint32_t* mm, int* flag, hipStream_t s);
 hipError_t launch_scale(const float* raw, size_t n, const uint32_t* mm, float* out, hipStream_t s);
+// Arguments of the reverse pass of one iteration (adjoint.hip).
+struct AdjArgs {
+  const float* x;          // [N] normalised intensities
+  const float* invg;       // [N] stored g_inv (sign: flat neighbourhood)
+  int32_t nx, ny, nz;
+  int32_t q2_sqdist;
+  float m, lam, xi;
+  const float* U;          // U^(t): the iteration's input (or the final state)
+  const float* c;          // c^(t) [C]
+  const float* Ubar_next;  // dJ/dU^(t+1) [N][C]         (iteration pass)
+  const double* cbar_next; // dJ/dc^(t+1) [C]            (iteration pass)
+  const float* c_next;     // c^(t+1) [C]                (iteration pass)
+  const double* B_next;    // eq (3) denominators of c^(t+1) [C]
+  float* PQ;               // [N][2C] transpose sources
+  float* Ubar_direct;      // [N][C] direct term of the objective-only pass
+  float* partials;         // [blocks][C + 2]
+};
+// Reverse of one iteration (eval = false) or of the final objective (eval =
+// true): writes dJ/dc of that state to cbar_out[C], adds dJ/dlambda and
+// dJ/dxi to acc2[0..1], and, if Ubar_out, dJ/dU of the state to Ubar_out.
+hipError_t launch_adjoint(int C, const AdjArgs& a, bool m2, bool eval, float* Ubar_out,
+                          double* cbar_out, double* acc2, hipStream_t s);
+size_t adjoint_slots(size_t N);
+
 // Resident work groups per CU of the gather / pointwise kernels.
 int gather_occupancy(int C, int ty, bool m2, bool step);
 int fcm_occupancy(int C, bool m2, bool step);
