@@ -147,13 +147,36 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
                            int32_t K, int32_t ckpt_every, double* J_out, double* dJ_dlambda,
                            double* dJ_dxi, double* dJ_dcentres);
 
-/* Pick the tile shape of the fused step for these volumes by timing the
- * candidates on the GPU; every candidate must reproduce the reference
- * candidate's results bit for bit before it may be chosen.  The choice is
- * kept in ctx and used by later calls with the same C, m == 2 and shapes.
- * best_out (host, may be NULL) receives a short description. */
+/* Pick the work decomposition of the fused step for these volumes -- waves
+ * per work group and planes per tile -- by timing a short batched swarm
+ * evaluation (P particles spread over [0, 1]^2, a few iterations from FCM
+ * memberships of evenly spaced centres) for each candidate.  A candidate is
+ * eligible only if its fitnesses and centres agree with the default
+ * decomposition's to 1e-5 relative (tilings change the order of the sums,
+ * nothing else).  The choice is kept in ctx for these (C, m == 2, shape)
+ * keys and used by later calls.  best_out (host, may be NULL) receives a
+ * short description (best_len bytes). */
 pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
                         const pifcm_params* p, int32_t P, char* best_out, int32_t best_len);
+
+/* Particle swarm search over (lambda, xi) in [0, 1]^2 -- Algorithm 1 steps
+ * 3-9 -- on B volumes at once, each volume with its own swarm of P
+ * particles; every generation evaluates all B * P fitnesses with one
+ * swarm_evaluate call (mode as there).  The paper's update has no inertia or
+ * coefficients and names no topology; this is the synchronous global-best
+ * swarm: v <- w v + c1 r1 (pbest - x) + c2 r2 (gbest - x), x <- clip(x + v,
+ * 0, 1), per particle and dimension, improvements only when strictly better,
+ * ties of the best to the lowest particle index.  All random numbers come
+ * from the caller: x0, v0 (host [P][2]) start every volume's swarm; r1, r2
+ * (host [G][P][2]) are the coefficients of generation g.  centres0, U0: the
+ * shared initial state of each volume (as in swarm_evaluate).
+ * Outputs (host): best_pos [B][2], best_fit [B], and optionally fit_hist
+ * [B][G][P] and pos_hist [B][G][P][2] (positions evaluated). */
+pifcm_status pifcm_pso(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, const pifcm_params* p,
+                       int32_t P, int32_t G, const double* x0, const double* v0, const double* r1,
+                       const double* r2, double w, double c1, double c2, const float* centres0,
+                       const float* const* U0, int32_t mode, double* best_pos, double* best_fit,
+                       double* fit_hist, double* pos_hist);
 
 /* Benchmark timing of the fused step launches.  While enabled, ifcm_solve
  * and swarm_evaluate record HIP events on the context's own stream before

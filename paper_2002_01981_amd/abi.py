@@ -107,6 +107,10 @@ def load_library(path=LIB_PATH):
     lib.ifcm_backward.restype = st
     lib.pifcm_tune.argtypes = [vp, P(_Volume), i32, P(_Params), i32, ct.c_char_p, i32]
     lib.pifcm_tune.restype = st
+    lib.pifcm_pso.argtypes = [vp, P(_Volume), i32, P(_Params), i32, i32, P(f64), P(f64), P(f64),
+                              P(f64), f64, f64, f64, P(f32), P(vp), i32, P(f64), P(f64), P(f64),
+                              P(f64)]
+    lib.pifcm_pso.restype = st
     lib.pifcm_set_timing.argtypes = [vp, i32]
     lib.pifcm_set_timing.restype = st
     lib.pifcm_get_timing.argtypes = [vp, P(f64), P(i64), i32]
@@ -272,3 +276,29 @@ class Context:
         buf = ct.create_string_buffer(256)
         self._check(self.lib.pifcm_tune(self.h, vols, B, ct.byref(p.c()), int(P), buf, 256))
         return buf.value.decode()
+
+    def pifcm_pso(self, xs, p: Params, streams, centres0, U0s, w=0.7, c1=1.5, c2=1.5,
+                  mode=PIFCM_SWARM_BATCHED):
+        """Global-best PSO on B volumes.  streams: dict(x0, v0 (P, 2), r1, r2
+        (G, P, 2)); centres0 (B, C); U0s: list of B (N_b, C) tensors.
+        Returns dict(best_pos (B, 2), best_fit (B,), fit_hist (B, G, P),
+        pos_hist (B, G, P, 2))."""
+        B = len(xs)
+        vols = (_Volume * B)(*[_volume(x) for x in xs])
+        x0 = np.ascontiguousarray(streams["x0"], np.float64)
+        v0 = np.ascontiguousarray(streams["v0"], np.float64)
+        r1 = np.ascontiguousarray(streams["r1"], np.float64)
+        r2 = np.ascontiguousarray(streams["r2"], np.float64)
+        G, P = r1.shape[0], r1.shape[1]
+        if x0.shape != (P, 2) or v0.shape != (P, 2) or r2.shape != (G, P, 2):
+            raise ValueError("stream shapes do not agree")
+        c0 = np.ascontiguousarray(centres0, np.float32).reshape(B, p.C)
+        ptrs = (ct.c_void_p * B)(*[_dev(u).data_ptr() for u in U0s])
+        bp = np.empty((B, 2))
+        bf = np.empty(B)
+        fh = np.empty((B, G, P))
+        ph = np.empty((B, G, P, 2))
+        self._check(self.lib.pifcm_pso(self.h, vols, B, ct.byref(p.c()), P, G, _dp(x0), _dp(v0),
+                                       _dp(r1), _dp(r2), float(w), float(c1), float(c2), _fp(c0),
+                                       ptrs, int(mode), _dp(bp), _dp(bf), _dp(fh), _dp(ph)))
+        return dict(best_pos=bp, best_fit=bf, fit_hist=fh, pos_hist=ph)

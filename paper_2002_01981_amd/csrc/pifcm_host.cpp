@@ -54,6 +54,7 @@ struct pifcm_ctx {
   int num_cu = 256;
   DevBuf invg, ubuf, partials, states, jhist, tvol, tpair, flags;
   DevBuf adj_ck, adj_seg, adj_bar, adj_pq, adj_misc;  // ifcm_backward workspace
+  DevBuf tune_u0, tune_state;                          // pifcm_tune workspace
   void* pinned = nullptr;
   size_t pinned_cap = 0;
   GraphCache graph;
@@ -355,7 +356,7 @@ void pifcm_destroy(pifcm_ctx* ctx) {
   if (ctx->graph.graph) (void)hipGraphDestroy(ctx->graph.graph);
   for (DevBuf* b : {&ctx->invg, &ctx->ubuf, &ctx->partials, &ctx->states, &ctx->jhist, &ctx->tvol,
                     &ctx->tpair, &ctx->flags, &ctx->adj_ck, &ctx->adj_seg, &ctx->adj_bar,
-                    &ctx->adj_pq, &ctx->adj_misc})
+                    &ctx->adj_pq, &ctx->adj_misc, &ctx->tune_u0, &ctx->tune_state})
     if (b->p) (void)hipFree(b->p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
@@ -946,8 +947,206 @@ pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
                         int32_t P, char* best_out, int32_t best_len) {
   if (!ctx) return PIFCM_E_INVALID;
   ctx->err.clear();
-  (void)vols; (void)B; (void)p; (void)P; (void)best_out; (void)best_len;
-  return fail(ctx, PIFCM_E_UNSUPPORTED, "pifcm_tune is not built yet");
+  if (!vols || B < 1 || B > kMaxBatchVols) return fail(ctx, PIFCM_E_INVALID, "B = %d outside [1, %d]", B, kMaxBatchVols);
+  if (P < 1 || (long)B * P > kMaxPairs) return fail(ctx, PIFCM_E_INVALID, "P = %d out of range", P);
+  TRY(check_params(ctx, p));
+  for (int b = 0; b < B; ++b) TRY(check_volume(ctx, &vols[b]));
+  const int C = p->C;
+  const bool m2 = p->m == 2.0f;
+  // Initial memberships: eq (2) with the attraction factor 1 for evenly
+  // spaced centres, one buffer per volume.
+  size_t total = 0;
+  std::vector<size_t> uoff(B);
+  for (int b = 0; b < B; ++b) {
+    uoff[b] = total;
+    total += (nvox(vols[b]) * C + 63) / 64 * 64;
+  }
+  TRY(begin(ctx));
+  TRY(ensure(ctx, ctx->tune_u0, total * sizeof(float), "tuning memberships"));
+  TRY(ensure(ctx, ctx->tune_state, sizeof(SolveState), "tuning state"));
+  TRY(ensure_pinned(ctx, sizeof(SolveState) + 4096));
+  std::vector<float> c0((size_t)B * C);
+  for (int b = 0; b < B; ++b)
+    for (int j = 0; j < C; ++j) c0[(size_t)b * C + j] = (float)(((double)j + 0.5) / C);
+  SolveState hs = init_state(c0.data(), C, 0.f, 0.f, p, nullptr);
+  std::memcpy(ctx->pinned, &hs, sizeof hs);
+  HIPCHK(hipMemcpyAsync(ctx->tune_state.p, ctx->pinned, sizeof hs, hipMemcpyHostToDevice, ctx->s));
+  std::vector<const float*> U0(B);
+  for (int b = 0; b < B; ++b) {
+    float* u = (float*)ctx->tune_u0.p + uoff[b];
+    HIPCHK(launch_init_u(C, vols[b].x, nvox(vols[b]), (const SolveState*)ctx->tune_state.p, p->m, m2, u,
+                         ctx->s));
+    U0[b] = u;
+  }
+  HIPCHK(hipStreamSynchronize(ctx->s));
+  TRY(finish(ctx));
+  // Particles on a regular grid over [0.05, 0.95]^2.
+  std::vector<float> parts((size_t)B * P * 2);
+  const int side = std::max(1, (int)std::ceil(std::sqrt((double)P)));
+  for (int q = 0; q < P; ++q) {
+    const float l = 0.05f + 0.9f * (float)(q % side) / (float)std::max(1, side - 1);
+    const float x = 0.05f + 0.9f * (float)(q / side) / (float)std::max(1, side - 1);
+    for (int b = 0; b < B; ++b) {
+      parts[((size_t)b * P + q) * 2] = l;
+      parts[((size_t)b * P + q) * 2 + 1] = x;
+    }
+  }
+  pifcm_params pt = *p;
+  pt.eps = 0.f;
+  pt.max_iter = std::max(2, std::min(p->max_iter, 4));
+  int maxz = 1;
+  for (int b = 0; b < B; ++b) maxz = std::max(maxz, vols[b].nz);
+  struct Cand { int nw, zc; };
+  std::vector<Cand> cands;
+  cands.push_back({4, 32});  // the default decomposition: the reference
+  const int nws[3] = {1, 2, 4};
+  const int zcs[4] = {8, 16, 32, 64};
+  for (int nw : nws) {
+    if (C != 4 && nw != 4) continue;
+    for (int zc : zcs) {
+      if (zc > maxz && zc != 8) continue;
+      if (nw == 4 && zc == 32) continue;
+      cands.push_back({nw, zc});
+    }
+  }
+  const bool was_timing = ctx->timing;
+  const auto saved = ctx->tuned;
+  std::vector<double> fit_ref((size_t)B * P), fit((size_t)B * P);
+  std::vector<float> cen_ref((size_t)B * P * C), cen((size_t)B * P * C);
+  double best_ms = 1e300;
+  Cand best = cands[0];
+  char desc[256] = {0};
+  for (size_t ci = 0; ci < cands.size(); ++ci) {
+    for (int b = 0; b < B; ++b) {
+      TileShape t;
+      t.nw = cands[ci].nw;
+      t.zc = cands[ci].zc;
+      ctx->tuned[std::make_tuple(C, (int)m2, vols[b].nx, vols[b].ny, vols[b].nz)] = t;
+    }
+    ctx->timing = false;
+    pifcm_status st = swarm_evaluate(ctx, vols, B, &pt, parts.data(), P, c0.data(), U0.data(),
+                                     fit.data(), cen.data(), nullptr, PIFCM_SWARM_BATCHED);
+    if (st == PIFCM_OK) {
+      ctx->timing = true;
+      const double ms0 = ctx->step_ms;
+      const int64_t n0 = ctx->step_launches;
+      st = swarm_evaluate(ctx, vols, B, &pt, parts.data(), P, c0.data(), U0.data(), fit.data(),
+                          cen.data(), nullptr, PIFCM_SWARM_BATCHED);
+      const double ms = (ctx->step_ms - ms0) / std::max<int64_t>(1, ctx->step_launches - n0);
+      ctx->step_ms = ms0;
+      ctx->step_launches = n0;
+      if (st == PIFCM_OK) {
+        bool ok = true;
+        if (ci == 0) {
+          fit_ref = fit;
+          cen_ref = cen;
+        } else {
+          for (size_t k = 0; k < fit.size(); ++k)
+            ok = ok && std::fabs(fit[k] - fit_ref[k]) <= 1e-5 * std::fabs(fit_ref[k]);
+          for (size_t k = 0; k < cen.size(); ++k)
+            ok = ok && std::fabs(cen[k] - cen_ref[k]) <= 1e-5f * std::max(1e-3f, std::fabs(cen_ref[k]));
+        }
+        if (ok && ms < best_ms) {
+          best_ms = ms;
+          best = cands[ci];
+        }
+      }
+    }
+    if (st != PIFCM_OK && ci == 0) {
+      ctx->timing = was_timing;
+      ctx->tuned = saved;
+      return st;
+    }
+  }
+  ctx->timing = was_timing;
+  ctx->tuned = saved;
+  for (int b = 0; b < B; ++b) {
+    TileShape t;
+    t.nw = best.nw;
+    t.zc = best.zc;
+    ctx->tuned[std::make_tuple(C, (int)m2, vols[b].nx, vols[b].ny, vols[b].nz)] = t;
+  }
+  snprintf(desc, sizeof desc, "waves_per_group=%d planes_per_tile=%d step_ms=%.4f candidates=%zu",
+           best.nw, best.zc, best_ms, cands.size());
+  if (best_out && best_len > 0) {
+    std::strncpy(best_out, desc, (size_t)best_len - 1);
+    best_out[best_len - 1] = 0;
+  }
+  ctx->err.clear();
+  return PIFCM_OK;
+}
+
+pifcm_status pifcm_pso(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, const pifcm_params* p,
+                       int32_t P, int32_t G, const double* x0, const double* v0, const double* r1,
+                       const double* r2, double w, double c1, double c2, const float* centres0,
+                       const float* const* U0, int32_t mode, double* best_pos, double* best_fit,
+                       double* fit_hist, double* pos_hist) {
+  if (!ctx) return PIFCM_E_INVALID;
+  ctx->err.clear();
+  if (B < 1 || B > kMaxBatchVols || P < 1 || G < 1 || (long)B * P > kMaxPairs)
+    return fail(ctx, PIFCM_E_INVALID, "B = %d, P = %d, G = %d out of range", B, P, G);
+  if (!x0 || !v0 || !r1 || !r2 || !best_pos || !best_fit)
+    return fail(ctx, PIFCM_E_INVALID, "x0, v0, r1, r2, best_pos and best_fit must be non-NULL");
+  if (!std::isfinite(w) || !std::isfinite(c1) || !std::isfinite(c2))
+    return fail(ctx, PIFCM_E_INVALID, "w, c1, c2 must be finite");
+  const int C = p ? p->C : 0;
+  std::vector<double> pos((size_t)B * P * 2), vel((size_t)B * P * 2), pb((size_t)B * P * 2);
+  std::vector<double> pbf((size_t)B * P), gb((size_t)B * 2), gbf(B);
+  std::vector<float> parts((size_t)B * P * 2);
+  std::vector<double> fit((size_t)B * P);
+  for (int b = 0; b < B; ++b)
+    for (int k = 0; k < P * 2; ++k) {
+      pos[(size_t)b * P * 2 + k] = x0[k];
+      vel[(size_t)b * P * 2 + k] = v0[k];
+    }
+  for (int g = 0; g < G; ++g) {
+    for (size_t k = 0; k < parts.size(); ++k) parts[k] = (float)pos[k];
+    TRY(swarm_evaluate(ctx, vols, B, p, parts.data(), P, centres0, U0, fit.data(), nullptr, nullptr,
+                       mode));
+    for (int b = 0; b < B; ++b) {
+      for (int q = 0; q < P; ++q) {
+        const size_t k = (size_t)b * P + q;
+        if (fit_hist) fit_hist[((size_t)b * G + g) * P + q] = fit[k];
+        if (pos_hist) {
+          pos_hist[(((size_t)b * G + g) * P + q) * 2] = pos[k * 2];
+          pos_hist[(((size_t)b * G + g) * P + q) * 2 + 1] = pos[k * 2 + 1];
+        }
+        if (g == 0 || fit[k] < pbf[k]) {  // step 5
+          pbf[k] = fit[k];
+          pb[k * 2] = pos[k * 2];
+          pb[k * 2 + 1] = pos[k * 2 + 1];
+        }
+      }
+      bool have = false;  // step 6, global best over the personal bests
+      for (int q = 0; q < P; ++q) {
+        const size_t k = (size_t)b * P + q;
+        if (!have || pbf[k] < gbf[b]) {
+          gbf[b] = pbf[k];
+          gb[b * 2] = pb[k * 2];
+          gb[b * 2 + 1] = pb[k * 2 + 1];
+          have = true;
+        }
+      }
+    }
+    if (g + 1 == G) break;
+    for (int b = 0; b < B; ++b)  // steps 7-8
+      for (int q = 0; q < P; ++q)
+        for (int d = 0; d < 2; ++d) {
+          const size_t k = ((size_t)b * P + q) * 2 + d;
+          const size_t s = ((size_t)g * P + q) * 2 + d;
+          const double v = w * vel[k] + c1 * r1[s] * (pb[k] - pos[k]) + c2 * r2[s] * (gb[b * 2 + d] - pos[k]);
+          const double np = pos[k] + v;
+          vel[k] = v;
+          pos[k] = np < 0.0 ? 0.0 : (np > 1.0 ? 1.0 : np);
+        }
+  }
+  for (int b = 0; b < B; ++b) {
+    best_pos[b * 2] = gb[b * 2];
+    best_pos[b * 2 + 1] = gb[b * 2 + 1];
+    best_fit[b] = gbf[b];
+  }
+  (void)C;
+  return PIFCM_OK;
 }
 
 }  // extern "C"

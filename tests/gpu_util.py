@@ -62,3 +62,42 @@ def check_labels(lab_gpu, U_ref, C, band=TIE_BAND):
 def random_memberships_f32(rng, n, C):
     a = rng.random((n, C)) + 0.05
     return (a / a.sum(1, keepdims=True)).astype(np.float32)
+
+
+def pso_replay(fit_hist, streams, w=0.7, c1=1.5, c2=1.5):
+    """Re-run the global-best swarm rules on given fitnesses (G, P).
+    Returns (pos_hist (G, P, 2), best_pos, best_fit, margin), where margin is
+    the smallest relative gap of any comparison the swarm decided: a
+    trajectory fed with fitnesses perturbed by less than that takes the
+    same decisions."""
+    G, P = fit_hist.shape
+    pos = np.array(streams["x0"], np.float64)
+    vel = np.array(streams["v0"], np.float64)
+    pb = pos.copy()
+    pbf = np.zeros(P)
+    margin = np.inf
+    ph = np.empty((G, P, 2))
+    gb = None
+    for g in range(G):
+        ph[g] = pos
+        for q in range(P):
+            f = fit_hist[g, q]
+            if g:
+                margin = min(margin, abs(f - pbf[q]) / abs(pbf[q]))
+            if g == 0 or f < pbf[q]:
+                pbf[q] = f
+                pb[q] = pos[q]
+        if P > 1:
+            o = np.sort(pbf)
+            margin = min(margin, (o[1] - o[0]) / abs(o[0]))
+        k = int(np.argmin(pbf))  # lowest index among equal minima
+        gb = pb[k].copy()
+        if g + 1 == G:
+            break
+        for q in range(P):
+            for d in range(2):
+                v = (w * vel[q, d] + c1 * streams["r1"][g, q, d] * (pb[q, d] - pos[q, d])
+                     + c2 * streams["r2"][g, q, d] * (gb[d] - pos[q, d]))
+                vel[q, d] = v
+                pos[q, d] = min(max(pos[q, d] + v, 0.0), 1.0)
+    return ph, gb, float(pbf.min()), margin
