@@ -45,9 +45,10 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(vol_raw, iters):
+def cpu_baseline(vol_raw, seconds):
     """The FP64 oracle, as it stands, on one (volume, particle) pair of the
-    workload for `iters` iterations on this host's cores."""
+    workload: IFCM steps at (lambda, xi) = (0.3, 0.4) on this host's cores
+    until about `seconds` of work (whole steps, at least two)."""
     import numpy as np
     import oracle
     x = oracle.normalize(vol_raw)
@@ -55,10 +56,48 @@ def cpu_baseline(vol_raw, iters):
     c = np.array([0.125, 0.375, 0.625, 0.875])
     U = oracle.init_memberships(x, c, p)
     t0 = time.perf_counter()
-    for _ in range(iters):
+    U, c, _ = oracle.step(x, U, c, p, 0.3, 0.4)
+    one = time.perf_counter() - t0
+    iters = max(2, int(round(seconds / max(one, 1e-6))))
+    for _ in range(iters - 1):
         U, c, _ = oracle.step(x, U, c, p, 0.3, 0.4)
     dt = time.perf_counter() - t0
-    return x.size * 4 * iters / dt, dt, oracle.get_threads()
+    return x.size * 4 * iters / dt, dt, iters, oracle.get_threads()
+
+
+def adjoint_leg(ctx, Params):
+    """Forward (K iterations) and backward (ifcm_backward) time on the brain
+    phantom of the differentiation workload, and the workspace it holds."""
+    import numpy as np
+    import torch
+    import synth
+    W = synth.WORKLOADS["adjoint-brain-K30"]
+    raw, _ = synth.brain_shells(shape=W["shape"], seed=W["seed"], noise_frac=W["noise_frac"])
+    x = ctx.pifcm_normalize(torch.from_numpy(raw).cuda())
+    c0, U0, _ = ctx.pifcm_fcm_init(x, Params(C=4, m=2.0, eps=0.0, max_iter=10))
+    K, s = W["K"], W["ckpt"]
+    lam, xi = W["points"][0]
+    pk = Params(C=4, m=2.0, eps=0.0, max_iter=K)
+    Uo = torch.empty_like(U0)
+    for _ in range(2):
+        ctx.ifcm_solve(x, pk, lam, xi, c0, U_in=U0, U_out=Uo)
+        ctx.ifcm_backward(x, Params(C=4, m=2.0), lam, xi, c0, U0, K, s)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.ifcm_solve(x, pk, lam, xi, c0, U_in=U0, U_out=Uo)
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        g = ctx.ifcm_backward(x, Params(C=4, m=2.0), lam, xi, c0, U0, K, s)
+    t2 = time.perf_counter()
+    fwd, bwd = (t1 - t0) * 1e3 / reps, (t2 - t1) * 1e3 / reps
+    return dict(workload="adjoint-brain-K30", volume_zyx=list(W["shape"]), K=K, ckpt_every=s,
+                point=[lam, xi], forward_ms=round(fwd, 3), backward_ms=round(bwd, 3),
+                backward_over_forward=round(bwd / fwd, 3),
+                workspace_bytes=ctx.workspace_bytes(), torch_allocated_bytes=int(base),
+                J=g["J"], dJ_dlambda=g["dlam"], dJ_dxi=g["dxi"])
 
 
 def main():
@@ -69,7 +108,10 @@ def main():
     ap.add_argument("--mode", choices=("batched", "plain"), default="batched")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-particle leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="length of the oracle's timed sample")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device copy of MIB MiB a few times (counter scaling)")
     args = ap.parse_args()
@@ -123,6 +165,13 @@ def main():
         for r, x in zip(raws, xs):
             ctx.pifcm_normalize(r, out=x)
         return ctx.swarm_evaluate(xs, p, particles, c0s, U0s, mode=m)
+
+    tune = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        desc = ctx.pifcm_tune(xs, Params(C=C, m=W["m"], eps=0.0, max_iter=4), P)
+        tune = dict(choice=desc, seconds=round(time.perf_counter() - t0, 3))
+        log(f"tuned: {desc}")
 
     for i in range(args.warmup):
         out = step()
@@ -178,13 +227,18 @@ def main():
                      bit_identical_to_batched=same)
         log(f"plain: {(tp1 - tp0) * 1e3:.1f} ms/step, identical={same}")
 
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = adjoint_leg(ctx, Params)
+        log(f"adjoint: forward {adjoint['forward_ms']} ms, backward {adjoint['backward_ms']} ms")
+
     cpu = None
     if not args.no_cpu_baseline:
         b = int(np.argmin(nvox))
-        rate, dt, cores = cpu_baseline(vols[b][0], args.cpu_iters)
+        rate, dt, iters, cores = cpu_baseline(vols[b][0], args.cpu_seconds)
         cpu = dict(value=rate, unit="voxel-cluster-iters/s", cores=cores, kind="oracle",
-                   sample=f"volume {b} ({dims[b][2]}x{dims[b][1]}x{dims[b][0]}), one particle, "
-                          f"{args.cpu_iters} iterations, {dt:.1f} s")
+                   sample=f"volume {b} of the batch ({dims[b][2]}x{dims[b][1]}x{dims[b][0]}), "
+                          f"one particle (0.3, 0.4), {iters} IFCM steps in {dt:.1f} s")
         log(f"cpu baseline: {rate:.3g} vci/s on {cores} threads in {dt:.1f}s")
 
     res = {
@@ -210,7 +264,9 @@ def main():
         },
         "hbm_GBps_algorithmic": round(achieved, 1),
         "roofline": roofline,
+        "tune": tune,
         "plain": plain,
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

@@ -178,6 +178,11 @@ pifcm_status pifcm_pso(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, cons
                        const float* const* U0, int32_t mode, double* best_pos, double* best_fit,
                        double* fit_hist, double* pos_hist);
 
+/* Device workspace the context holds (bytes, host outputs; either may be
+ * NULL): the sum of its device buffers, which only grow, so this is also the
+ * peak since pifcm_create, and its pinned host staging buffer. */
+pifcm_status pifcm_workspace_bytes(pifcm_ctx* ctx, int64_t* device_bytes, int64_t* pinned_bytes);
+
 /* Benchmark timing of the fused step launches.  While enabled, ifcm_solve
  * and swarm_evaluate record HIP events on the context's own stream before
  * their first and after their last step launch (the launches are queued back

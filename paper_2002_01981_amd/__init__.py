@@ -13,3 +13,4 @@ from .abi import (  # noqa: F401
     load_library,
     header_symbols,
 )
+from .pipeline import ifcm_objective, refine, segment  # noqa: F401,E402

@@ -111,6 +111,8 @@ def load_library(path=LIB_PATH):
                               P(f64), f64, f64, f64, P(f32), P(vp), i32, P(f64), P(f64), P(f64),
                               P(f64)]
     lib.pifcm_pso.restype = st
+    lib.pifcm_workspace_bytes.argtypes = [vp, P(i64), P(i64)]
+    lib.pifcm_workspace_bytes.restype = st
     lib.pifcm_set_timing.argtypes = [vp, i32]
     lib.pifcm_set_timing.restype = st
     lib.pifcm_get_timing.argtypes = [vp, P(f64), P(i64), i32]
@@ -260,6 +262,12 @@ class Context:
                                            float(xi), _fp(c), _dev(U0).data_ptr(), int(K),
                                            int(ckpt_every), _dp(J), _dp(dl), _dp(dx), _dp(dc)))
         return dict(J=float(J[0]), dlam=float(dl[0]), dxi=float(dx[0]), dc=dc)
+
+    def workspace_bytes(self):
+        """Device bytes of workspace the context holds (its peak so far)."""
+        d, h = ct.c_int64(), ct.c_int64()
+        self._check(self.lib.pifcm_workspace_bytes(self.h, ct.byref(d), ct.byref(h)))
+        return int(d.value)
 
     def pifcm_set_timing(self, enable=True):
         self._check(self.lib.pifcm_set_timing(self.h, 1 if enable else 0))

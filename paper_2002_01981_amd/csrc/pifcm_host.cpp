@@ -396,6 +396,20 @@ pifcm_status pifcm_get_timing(pifcm_ctx* ctx, double* step_ms, int64_t* step_lau
   return PIFCM_OK;
 }
 
+pifcm_status pifcm_workspace_bytes(pifcm_ctx* ctx, int64_t* device_bytes, int64_t* pinned_bytes) {
+  if (!ctx) return PIFCM_E_INVALID;
+  ctx->err.clear();
+  int64_t d = 0;
+  for (const DevBuf* b : {&ctx->invg, &ctx->ubuf, &ctx->partials, &ctx->states, &ctx->jhist,
+                          &ctx->tvol, &ctx->tpair, &ctx->flags, &ctx->adj_ck, &ctx->adj_seg,
+                          &ctx->adj_bar, &ctx->adj_pq, &ctx->adj_misc, &ctx->tune_u0,
+                          &ctx->tune_state})
+    d += (int64_t)b->cap;
+  if (device_bytes) *device_bytes = d;
+  if (pinned_bytes) *pinned_bytes = (int64_t)ctx->pinned_cap;
+  return PIFCM_OK;
+}
+
 pifcm_status pifcm_normalize(pifcm_ctx* ctx, const float* raw, int64_t n, float* x_out) {
   if (!ctx) return PIFCM_E_INVALID;
   ctx->err.clear();

@@ -1,0 +1,148 @@
+"""Parity at the full sizes of the paper-shaped workloads.
+
+A whole PSO campaign of the oracle at these sizes takes hours, so each test
+runs the GPU path at its real size and launch configuration and checks what
+the oracle computes in one pass over the volume: one IFCM step from the
+GPU's own state after t iterations (memberships of every voxel, centres, J
+of the input state, labels), and the final fitness as J of the GPU's final
+state.  The batched swarm launch at the benchmark's configuration is tied to
+those checks by bit-identity with the plain launch and with lone solves.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import (SATURATED_TIE_BAND, TIE_BAND, TOL, check_labels, dev, host, rel, rel2,
+                      saturated)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "the GPU tests need a GPU"
+    from paper_2002_01981_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _P(**kw):
+    from paper_2002_01981_amd import Params
+    return Params(**kw)
+
+
+def _normalised(ctx, raw):
+    xo = oracle.normalize(raw)
+    xg = ctx.pifcm_normalize(dev(raw))
+    assert np.array_equal(host(xg), xo)
+    return xo, xg
+
+
+def _one_step_check(ctx, xo, xg, c0, U0, lam, xi, t):
+    """t GPU iterations from (c0, U0), then one more on both sides from the
+    GPU's state."""
+    st = ctx.ifcm_solve(xg, _P(C=4, m=2.0, eps=0.0, max_iter=t), lam, xi, c0, U_in=U0)
+    g = ctx.ifcm_solve(xg, _P(C=4, m=2.0, eps=0.0, max_iter=1), lam, xi, st["c"], U_in=st["U"],
+                       labels=True, want_hist=True)
+    Uo, co, Jo = oracle.step(xo, host(st["U"]).astype(np.float64), st["c"].astype(np.float64),
+                             oracle.Params(C=4, m=2.0), lam, xi)
+    sat = saturated(lam, xi)
+    assert (rel2 if sat else rel)(host(g["U"]), Uo) <= TOL
+    assert rel(g["c"], co) <= TOL
+    assert abs(g["J_hist"][0] - Jo) <= TOL * abs(Jo)
+    check_labels(host(g["labels"]), Uo, 4, SATURATED_TIE_BAND if sat else TIE_BAND)
+
+
+def test_ellipsoids_854x854x16(ctx):
+    W = synth.WORKLOADS["ellipsoids-854x854x16"]
+    raw, _ = synth.random_ellipsoids(shape=W["shape"], seed=W["seed"], sigma=W["sigma"])
+    xo, xg = _normalised(ctx, raw)
+    c0, U0, _ = ctx.pifcm_fcm_init(xg, _P(C=4, m=2.0, eps=W["eps"], max_iter=W["max_iter"]))
+    for lam, xi, t in ((0.0, 0.0, 0), (0.3, 0.4, 6), (0.9, 0.7, 3)):
+        _one_step_check(ctx, xo, xg, c0, U0, lam, xi, t)
+
+
+def test_brain_181x217x181(ctx):
+    W = synth.WORKLOADS["brain-181x217x181"]
+    raw, _ = synth.brain_shells(shape=W["shape"], seed=W["seed"], noise_frac=W["noise_frac"])
+    xo, xg = _normalised(ctx, raw)
+    c0, U0, _ = ctx.pifcm_fcm_init(xg, _P(C=4, m=2.0, eps=W["eps"], max_iter=W["max_iter"]))
+    for lam, xi, t in ((0.2, 0.5, 5), (0.6, 0.3, 2)):
+        _one_step_check(ctx, xo, xg, c0, U0, lam, xi, t)
+
+
+def test_ragged_swarm_in_benchmark_configuration(ctx):
+    """Six ragged volumes x 64 particles x 20 iterations, tuned tile shapes,
+    one batched launch per iteration -- as the benchmark times it."""
+    from paper_2002_01981_amd import PIFCM_SWARM_PLAIN
+    W = synth.WORKLOADS["ragged6-swarm64"]
+    dims = synth.ragged_dims(W["seed"], W["count"])
+    vols = synth.ragged_batch(seed=W["seed"], count=W["count"], sigma=W["sigma"], dims=dims)
+    xs, c0s, U0s = [], [], []
+    for raw, _ in vols:
+        xo, xg = _normalised(ctx, raw)
+        c, U0, _ = ctx.pifcm_fcm_init(xg, _P(C=4, m=2.0, eps=1e-5, max_iter=50))
+        xs.append((xo, xg))
+        c0s.append(c)
+        U0s.append(U0)
+    c0s = np.stack(c0s)
+    xg = [x for _, x in xs]
+    P, T = W["particles"], W["iters"]
+    parts = np.ascontiguousarray(np.broadcast_to(synth.uniform_particles(W["particle_seed"], P),
+                                                 (len(xg), P, 2)))
+    p = _P(C=4, m=2.0, eps=0.0, max_iter=T)
+    default = ctx.swarm_evaluate(xg, p, parts, c0s, U0s)
+    plain = ctx.swarm_evaluate(xg, p, parts, c0s, U0s, mode=PIFCM_SWARM_PLAIN)
+    assert np.array_equal(default["fitness"], plain["fitness"])
+    assert np.array_equal(default["centres"], plain["centres"])
+    assert np.all(default["iters"] == T)
+    ctx.pifcm_tune(xg, _P(C=4, m=2.0, eps=0.0, max_iter=4), P)
+    tuned = ctx.swarm_evaluate(xg, p, parts, c0s, U0s)
+    assert np.max(np.abs(tuned["fitness"] / default["fitness"] - 1.0)) <= 1e-5
+    # sampled pairs: a lone solve with the same (tuned) tiles is bit-identical,
+    # and the oracle's J of the GPU's final state is the fitness
+    b = int(np.argmin([x.size for x, _ in xs]))
+    for q in (0, 17, 63):
+        lam, xi = (float(v) for v in parts[b, q])
+        s = ctx.ifcm_solve(xg[b], p, lam, xi, c0s[b], U_in=U0s[b])
+        assert s["J"] == tuned["fitness"][b, q]
+        assert np.array_equal(s["c"], tuned["centres"][b, q])
+    _, _, Jo = oracle.step(xs[b][0], host(s["U"]).astype(np.float64), s["c"].astype(np.float64),
+                           oracle.Params(C=4, m=2.0), lam, xi)
+    assert abs(tuned["fitness"][b, 63] - Jo) <= TOL * abs(Jo)
+
+
+def test_adjoint_brain_K30(ctx):
+    """The differentiation workload at full size: 181x217x181, K = 30,
+    checkpoints every 5.  The adjoint's dJ/dlambda and dJ/dxi must match
+    central differences of the GPU's own J_K (h = 1e-2, where the float32
+    noise of J_K stays far below the bar), and its directional derivative
+    along the centres one along a random unit direction."""
+    W = synth.WORKLOADS["adjoint-brain-K30"]
+    raw, _ = synth.brain_shells(shape=W["shape"], seed=W["seed"], noise_frac=W["noise_frac"])
+    _, xg = _normalised(ctx, raw)
+    c0, U0, _ = ctx.pifcm_fcm_init(xg, _P(C=4, m=2.0, eps=0.0, max_iter=10))
+    K, s = W["K"], W["ckpt"]
+    pk = _P(C=4, m=2.0, eps=0.0, max_iter=K)
+
+    def JK(lam, xi, c):
+        return ctx.ifcm_solve(xg, pk, lam, xi, c.astype(np.float32), U_in=U0)["J"]
+
+    rng = np.random.default_rng(7)
+    d = rng.normal(size=4)
+    d /= np.linalg.norm(d)
+    h = 1e-2
+    for lam, xi in W["points"]:
+        g = ctx.ifcm_backward(xg, _P(C=4, m=2.0), lam, xi, c0, U0, K, s)
+        c = c0.astype(np.float64)
+        assert abs(g["J"] - JK(lam, xi, c)) <= 1e-6 * abs(g["J"])
+        fd_l = (JK(lam + h, xi, c) - JK(lam - h, xi, c)) / (2 * h)
+        fd_x = (JK(lam, xi + h, c) - JK(lam, xi - h, c)) / (2 * h)
+        hc = 1e-3
+        fd_c = (JK(lam, xi, c + hc * d) - JK(lam, xi, c - hc * d)) / (2 * hc)
+        ref = np.array([fd_l, fd_x, fd_c])
+        got = np.array([g["dlam"], g["dxi"], float(g["dc"] @ d)])
+        assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) <= 1e-3, (lam, xi, got, ref)

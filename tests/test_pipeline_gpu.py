@@ -1,0 +1,152 @@
+"""Algorithm 1 end to end (segment), the autograd wrapper of J_K and the
+gradient refinement of a particle, on the GPU against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import TOL, check_labels, dev, host, pso_replay, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "the GPU tests need a GPU"
+    from paper_2002_01981_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _P(**kw):
+    from paper_2002_01981_amd import Params
+    return Params(**kw)
+
+
+def _sensitivity(xo, c0, U0, po, lam, xi, delta=1e-6):
+    """Relative change of the oracle's fitness at (lam, xi) when U0 is
+    perturbed by `delta` (relative, seeded): the amplification of a
+    perturbation of that size along the whole solve."""
+    a = oracle.solve(xo, c0, po, lam, xi, U0=U0)["J"]
+    rng = np.random.default_rng(0)
+    Up = U0 * (1.0 + delta * rng.standard_normal(U0.shape))
+    Up /= Up.sum(1, keepdims=True)
+    b = oracle.solve(xo, c0, po, lam, xi, U0=Up)["J"]
+    return abs(a - b) / abs(a)
+
+
+def test_segment_nested32_matches_oracle(ctx):
+    """The CPU-sized workload: 32x32x8 nested ellipsoids, C = 4, m = 2,
+    eps = 1e-5, at most 50 iterations, swarm of 8 particles x 5 generations
+    (w = 0.7, c1 = c2 = 1.5), everything from the GPU's FCM initial state
+    (handed to the oracle in float32).
+
+    For lambda + xi well above 1 the iteration does not converge (it settles
+    into an oscillation) and its fitness after 50 iterations depends on
+    rounding: a 1e-6 perturbation of U0 moves the oracle's own result by up
+    to ~1e0.  Such evaluations cannot agree between float32 and float64; an
+    evaluation is held to the bar when that perturbation moves the oracle's
+    fitness by at most 1e-6, and the swarms are compared up to the first
+    generation that holds an ill-conditioned evaluation."""
+    from paper_2002_01981_amd import segment
+    W = synth.WORKLOADS["nested-32x32x8"]
+    raw, _ = synth.nested_ellipsoids(shape=W["shape"], seed=W["seed"], sigma=W["sigma"])
+    xo = oracle.normalize(raw)
+    xg = ctx.pifcm_normalize(dev(raw))
+    assert np.array_equal(host(xg), xo)
+    ps = W["pso"]
+    st = synth.pso_streams(ps["seed"], ps["P"], ps["G"])
+    p = _P(C=4, m=2.0, eps=W["eps"], max_iter=W["max_iter"])
+    g = segment(ctx, xg, p, st, w=ps["w"], c1=ps["c1"], c2=ps["c2"])
+
+    po = oracle.Params(C=4, m=2.0, eps=W["eps"], max_iter=W["max_iter"])
+    c0o, _, _ = oracle.fcm_init(xo, po)
+    assert rel(g["centres0"], c0o) <= TOL
+    c0 = g["centres0"].astype(np.float64)
+    _, U0g, _ = ctx.pifcm_fcm_init(xg, p)
+    U0 = host(U0g).astype(np.float64)
+
+    # the GPU's swarm follows its rules on its own fitnesses
+    ph, gb, bf, _ = pso_replay(g["fit_hist"], st, ps["w"], ps["c1"], ps["c2"])
+    assert np.max(np.abs(ph - g["pos_hist"])) <= 1e-12
+    assert np.max(np.abs(gb - g["best_pos"])) <= 1e-12 and bf == g["best_fit"]
+
+    # every well-conditioned evaluation matches the oracle at the same particle
+    G, P = g["fit_hist"].shape
+    well = np.zeros((G, P), bool)
+    for gen in range(G):
+        for q in range(P):
+            lam, xi = (float(v) for v in np.float32(g["pos_hist"][gen, q]))
+            if _sensitivity(xo, c0, U0, po, lam, xi) > 1e-6:
+                continue
+            well[gen, q] = True
+            o = oracle.solve(xo, c0, po, lam, xi, U0=U0)
+            assert abs(g["fit_hist"][gen, q] - o["J"]) <= TOL * abs(o["J"]), (gen, q)
+    assert well.mean() >= 0.5
+    assert well[0].all()
+
+    # the oracle's swarm takes the same path while every evaluation is
+    # well-conditioned (and its decisions are not near-ties)
+    o = oracle.pso(xo, c0, U0, po, st, w=ps["w"], c1=ps["c1"], c2=ps["c2"])
+    ok = int(np.argmin(well.all(axis=1))) if not well.all() else G
+    assert pso_replay(o["fit_hist"][:ok], st, ps["w"], ps["c1"], ps["c2"])[3] > 1e-3
+    assert np.max(np.abs(g["pos_hist"][:ok + 1] - o["pos_hist"][:ok + 1])) <= 1e-12
+
+    # final solve at the best particle (Algorithm 1, step 11)
+    lam, xi = (float(v) for v in np.float32(g["best_pos"]))
+    U = host(g["U"])
+    assert np.max(np.abs(U.sum(1) - 1.0)) <= 1e-5
+    assert np.array_equal(host(g["labels"]), np.argmax(U, axis=1))
+    if _sensitivity(xo, c0, U0, po, lam, xi) <= 1e-6:
+        fin = oracle.solve(xo, c0, po, lam, xi, U0=U0)
+        assert g["iters"] == fin["iters"]
+        assert rel(U, fin["U"]) <= TOL
+        assert rel(g["centres"], fin["c"]) <= TOL
+        assert abs(g["J"] - fin["J"]) <= TOL * abs(fin["J"])
+        check_labels(host(g["labels"]), fin["U"], 4)
+
+
+def _small_case(shape=(9, 16, 21), seed=80, C=4):
+    raw, _ = synth.random_ellipsoids(shape=shape, seed=seed, sigma=0.07)
+    x = oracle.normalize(raw)
+    c0, U0, _ = oracle.fcm_init(x, oracle.Params(C=C, m=2.0, eps=0.0, max_iter=8))
+    return x, c0.astype(np.float32), U0.astype(np.float32)
+
+
+def test_autograd_function_gradient(ctx):
+    import torch
+    from paper_2002_01981_amd import ifcm_objective
+    x, c0, U0 = _small_case()
+    p = _P(C=4, m=2.0)
+    K, s = 7, 3
+    params = torch.tensor([0.25, 0.35, *c0.astype(np.float64)], dtype=torch.float64,
+                          requires_grad=True)
+    J = ifcm_objective().apply(ctx, dev(x), p, dev(U0), K, s, params)
+    (2.0 * J).backward()
+    g = ctx.ifcm_backward(dev(x), p, 0.25, 0.35, c0, dev(U0), K, s)
+    ref = 2.0 * np.concatenate([[g["dlam"], g["dxi"]], g["dc"]])
+    assert float(J) == g["J"]
+    assert np.array_equal(params.grad.numpy(), ref)
+    Jo, go = oracle.fd_grad(x, c0.astype(np.float64), U0.astype(np.float64),
+                            oracle.Params(C=4, m=2.0), 0.25, 0.35, K=K, step=1e-4)
+    assert abs(float(J) - Jo) <= TOL * abs(Jo)
+    assert np.max(np.abs(params.grad.numpy() / 2.0 - go)) / np.max(np.abs(go)) <= 1e-3
+
+
+def test_refine_descends_inside_the_box(ctx):
+    from paper_2002_01981_amd import refine
+    x, c0, U0 = _small_case(seed=81)
+    p = _P(C=4, m=2.0)
+    K, s = 10, 5
+    r = refine(ctx, dev(x), p, 0.3, 0.2, c0, dev(U0), K, s, steps=6, lr=0.05)
+    Js = [h[2] for h in r["history"]]
+    assert all(b < a for a, b in zip(Js, Js[1:]))
+    assert len(Js) >= 2  # at least one accepted step from an interior point
+    assert np.all((r["pos"] >= 0.0) & (r["pos"] <= 1.0))
+    assert r["J"] <= Js[0]
+    lam, xi = (float(v) for v in np.float32(r["pos"]))
+    o = oracle.solve(x, c0.astype(np.float64), oracle.Params(C=4, m=2.0, eps=0.0, max_iter=K),
+                     lam, xi, U0=U0.astype(np.float64))
+    assert abs(r["J"] - o["J"]) <= TOL * abs(o["J"])
