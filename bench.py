@@ -65,12 +65,13 @@ def cpu_baseline(vol_raw, seconds):
     return x.size * 4 * iters / dt, dt, iters, oracle.get_threads()
 
 
-def adjoint_leg(ctx, Params):
+def adjoint_leg(Context, Params):
     """Forward (K iterations) and backward (ifcm_backward) time on the brain
-    phantom of the differentiation workload, and the workspace it holds."""
-    import numpy as np
+    phantom of the differentiation workload, and the workspace its own
+    context holds."""
     import torch
     import synth
+    ctx = Context(0)
     W = synth.WORKLOADS["adjoint-brain-K30"]
     raw, _ = synth.brain_shells(shape=W["shape"], seed=W["seed"], noise_frac=W["noise_frac"])
     x = ctx.pifcm_normalize(torch.from_numpy(raw).cuda())
@@ -93,10 +94,12 @@ def adjoint_leg(ctx, Params):
         g = ctx.ifcm_backward(x, Params(C=4, m=2.0), lam, xi, c0, U0, K, s)
     t2 = time.perf_counter()
     fwd, bwd = (t1 - t0) * 1e3 / reps, (t2 - t1) * 1e3 / reps
+    ws = ctx.workspace_bytes()
+    ctx.close()
     return dict(workload="adjoint-brain-K30", volume_zyx=list(W["shape"]), K=K, ckpt_every=s,
                 point=[lam, xi], forward_ms=round(fwd, 3), backward_ms=round(bwd, 3),
                 backward_over_forward=round(bwd / fwd, 3),
-                workspace_bytes=ctx.workspace_bytes(), torch_allocated_bytes=int(base),
+                workspace_bytes=ws, torch_allocated_bytes=int(base),
                 J=g["J"], dJ_dlambda=g["dlam"], dJ_dxi=g["dxi"])
 
 
@@ -229,7 +232,7 @@ def main():
 
     adjoint = None
     if not args.no_adjoint:
-        adjoint = adjoint_leg(ctx, Params)
+        adjoint = adjoint_leg(Context, Params)
         log(f"adjoint: forward {adjoint['forward_ms']} ms, backward {adjoint['backward_ms']} ms")
 
     cpu = None

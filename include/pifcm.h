@@ -62,13 +62,19 @@ pifcm_status pifcm_set_stream(pifcm_ctx* ctx, void* hip_stream);
 const char* pifcm_last_error(const pifcm_ctx* ctx);
 
 /* Readings of passages the paper leaves open (flags). */
-#define PIFCM_Q2_SQDIST 2 /* weight q (eq (8)) instead of q^2 in eq (7) */
+#define PIFCM_SHELL_SQDIST 1 /* rings of eqs (5), (7), (10) by squared distance
+                                dX^2 + dY^2 + dZ^2 = 1..V instead of the
+                                Chebyshev shells max(|dX|, |dY|, |dZ|) = 1..V */
+#define PIFCM_Q2_SQDIST 2    /* weight q (eq (8)) instead of q^2 in eq (7) */
 
 typedef struct {
   int32_t C;        /* c: number of clusters, 2..16 (Algorithm 1 input)          */
   float m;          /* m: fuzziness, > 1 (Algorithm 1 input)                      */
-  int32_t V;        /* v: depth = number of rings; 1 = the 3x3x3 neighbourhood   */
-  float h;          /* h: exponential decay of eq (10); unused when V == 1       */
+  int32_t V;        /* v: depth = number of rings; 1 = the 3x3x3 neighbourhood.
+                       Chebyshev rings: V <= 3; with PIFCM_SHELL_SQDIST: V <= 15
+                       (cells at most 3 apart along each axis)                */
+  float h;          /* h: decay of eq (10), W_r ~ exp(-(r - 1) / h), > 0; only
+                       matters with more than one ring                         */
   float eps;        /* epsilon: stop after iteration t >= 2 once
                        |J(t-1) - J(t-2)| <= eps * |J(t-2)|; 0 = run max_iter       */
   int32_t max_iter; /* iteration cap, >= 0                                       */
@@ -102,7 +108,9 @@ pifcm_status pifcm_normalize(pifcm_ctx* ctx, const float* raw, int64_t n, float*
  * defined when the attraction factor is <= 0 or a voxel equals a centre.
  * lambda and xi may lie outside [0, 1] but must satisfy |.| <= 1000
  * (PIFCM_E_INVALID otherwise).
- * PIFCM_E_UNSUPPORTED for V > 1. */
+ * V = 1 without PIFCM_SHELL_SQDIST runs the fused 3x3x3 kernel; other
+ * neighbourhoods run a general kernel (one voxel per thread, neighbours read
+ * through the caches).  PIFCM_E_UNSUPPORTED beyond the V limits above. */
 pifcm_status ifcm_solve(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
                         float lambda, float xi, const float* centres_in, const float* U_in,
                         float* U_out, float* centres_out, uint8_t* labels_out, double* J_out,
@@ -141,7 +149,9 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
  * respect to lambda, xi and the initial centres, by a hand-written adjoint
  * of the K unrolled iterations.  Memberships are kept every ckpt_every
  * iterations (1 <= ckpt_every <= K) and recomputed segment by segment.
- * Outputs (host): J_out, dJ_dlambda, dJ_dxi, dJ_dcentres [C]. */
+ * Outputs (host): J_out, dJ_dlambda, dJ_dxi, dJ_dcentres [C].
+ * Built for the 3x3x3 neighbourhood (V = 1 without PIFCM_SHELL_SQDIST);
+ * PIFCM_E_UNSUPPORTED otherwise. */
 pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
                            float lambda, float xi, const float* centres0, const float* U0,
                            int32_t K, int32_t ckpt_every, double* J_out, double* dJ_dlambda,
@@ -155,7 +165,8 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
  * decomposition's to 1e-5 relative (tilings change the order of the sums,
  * nothing else).  The choice is kept in ctx for these (C, m == 2, shape)
  * keys and used by later calls.  best_out (host, may be NULL) receives a
- * short description (best_len bytes). */
+ * short description (best_len bytes).  The general-neighbourhood kernel has
+ * a fixed decomposition: for those parameters nothing is timed. */
 pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
                         const pifcm_params* p, int32_t P, char* best_out, int32_t best_len);
 

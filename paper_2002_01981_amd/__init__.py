@@ -10,6 +10,7 @@ from .abi import (  # noqa: F401
     PIFCM_SWARM_BATCHED,
     PIFCM_SWARM_PLAIN,
     PIFCM_Q2_SQDIST,
+    PIFCM_SHELL_SQDIST,
     load_library,
     header_symbols,
 )

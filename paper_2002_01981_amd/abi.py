@@ -25,6 +25,7 @@ PIFCM_E_NONFINITE = -2
 PIFCM_E_OOM = -3
 PIFCM_E_HIP = -4
 PIFCM_E_UNSUPPORTED = -5
+PIFCM_SHELL_SQDIST = 1
 PIFCM_Q2_SQDIST = 2
 PIFCM_SWARM_BATCHED = 0
 PIFCM_SWARM_PLAIN = 1

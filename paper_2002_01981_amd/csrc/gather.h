@@ -15,7 +15,7 @@
 // lane owns one (x, y) column and walks it along z.  Waves never wait for
 // each other -- each has a private LDS region -- so there is no work-group
 // barrier anywhere in the kernel.  Each plane of the tile plus a one-voxel
-// halo (18 x 6 cells) is staged once in the wave's LDS (double-buffered) and
+// halo (18 x 6 cells) is staged once in the wave's LDS (triple-buffered) and
 // every lane reads its 3x3 in-plane cells once: they contribute to three
 // voxels of its column at the same time -- z-1 (the plane is its upper
 // neighbour plane), z (its own plane) and z+1 (lower plane).  The partial
@@ -42,8 +42,9 @@
 //   * cells outside the volume are staged with u = 0, so they add nothing to
 //     any sum.
 // Sums over voxels are per-lane in fp32, reduced per tile in a fixed
-// butterfly order, and combined over tiles in fp64 by the last tile of the
-// pair to finish (no floating-point atomics: results are bit-reproducible).
+// butterfly order into the tile's own slot; k_finalize then adds the slots of
+// each pair in fp64 in tile order (no floating-point atomics: results are
+// bit-reproducible).
 #pragma once
 #include "common.h"
 

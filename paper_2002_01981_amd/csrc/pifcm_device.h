@@ -55,6 +55,16 @@ struct PairDev {
   float* partials;     // [tiles][2C + 1] per-tile sums of one launch
 };
 
+// General neighbourhoods (rings V >= 1, eqs (5), (7), (9), (10)): offsets
+// sorted by ring, at most kMaxReach cells away along each axis.
+constexpr int kMaxReach = 3;
+constexpr int kMaxRings = 15;
+struct RingOff {
+  int16_t dx, dy, dz, ring;  // offset and its ring index r (1..V)
+  float q2;                  // eq (7) spatial weight of the offset
+  float pad;
+};
+
 // Arguments of a fused launch over volumes [0, nvol) x particles [0, P).
 // Pairs are ordered volume-major: pair (b, p) = pairs[b * P + p]; work items
 // are ordered pair-major then tile, so adjacent tiles of one pair are
@@ -69,6 +79,10 @@ struct LaunchArgs {
   float m;
   int32_t use_1d;      // items are 1D voxel blocks (pointwise kernels)
   int32_t item_begin[kMaxBatchVols + 1];  // first item of each volume
+  const RingOff* ring; // general-neighbourhood offsets (ring kernel only)
+  int32_t nring;       // number of offsets
+  int32_t pad1;
+  float W[kMaxRings + 1];  // eq (10) weight of ring r at W[r]
 };
 
 __host__ __device__ inline const float* u_in_of(const PairDev& pr, int t) {

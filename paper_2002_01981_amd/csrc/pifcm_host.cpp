@@ -55,6 +55,11 @@ struct pifcm_ctx {
   DevBuf invg, ubuf, partials, states, jhist, tvol, tpair, flags;
   DevBuf adj_ck, adj_seg, adj_bar, adj_pq, adj_misc;  // ifcm_backward workspace
   DevBuf tune_u0, tune_state;                          // pifcm_tune workspace
+  DevBuf ring_tab;                                     // general-neighbourhood offsets
+  int ring_n = 0;                                      // offsets in ring_tab
+  int ring_gen = 0;                                    // rebuilds of ring_tab
+  int ring_key[3] = {0, -1, 0};                        // (V, flags, bits of h) of ring_tab
+  float ring_W[kMaxRings + 1] = {};                    // eq (10) weights by ring
   void* pinned = nullptr;
   size_t pinned_cap = 0;
   GraphCache graph;
@@ -168,8 +173,13 @@ pifcm_status check_params(pifcm_ctx* ctx, const pifcm_params* p) {
   if (!std::isfinite(p->h) || !(p->h > 0.f)) return fail(ctx, PIFCM_E_INVALID, "h = %g must be finite and > 0", p->h);
   if (!std::isfinite(p->eps) || p->eps < 0.f) return fail(ctx, PIFCM_E_INVALID, "eps = %g must be finite and >= 0", p->eps);
   if (p->max_iter < 0 || p->max_iter > 1000000) return fail(ctx, PIFCM_E_INVALID, "max_iter = %d outside [0, 1e6]", p->max_iter);
-  if (p->flags & ~PIFCM_Q2_SQDIST) return fail(ctx, PIFCM_E_INVALID, "unknown flags 0x%x", p->flags);
-  if (p->V > 1) return fail(ctx, PIFCM_E_UNSUPPORTED, "V = %d: only the 3x3x3 neighbourhood (V = 1) is built", p->V);
+  if (p->flags & ~(PIFCM_Q2_SQDIST | PIFCM_SHELL_SQDIST))
+    return fail(ctx, PIFCM_E_INVALID, "unknown flags 0x%x", p->flags);
+  if ((p->flags & PIFCM_SHELL_SQDIST) && p->V > kMaxRings)
+    return fail(ctx, PIFCM_E_UNSUPPORTED, "V = %d: squared-distance rings are built up to V = %d", p->V,
+                kMaxRings);
+  if (!(p->flags & PIFCM_SHELL_SQDIST) && p->V > kMaxReach)
+    return fail(ctx, PIFCM_E_UNSUPPORTED, "V = %d: Chebyshev rings are built up to V = %d", p->V, kMaxReach);
   return PIFCM_OK;
 }
 
@@ -279,17 +289,90 @@ SolveState init_state(const float* c0, int C, float lam, float xi, const pifcm_p
   return s;
 }
 
+// Which step kernel a launch uses.
+enum Kind { kGather = 0, kFcm = 1, kRing = 2 };
+
+bool ring_params(const pifcm_params* p) { return p->V > 1 || (p->flags & PIFCM_SHELL_SQDIST); }
+
+// lambda = xi = 0 makes the attraction factor of eq (4) exactly 1 for every
+// neighbourhood: plain FCM.
+int kind_of(const pifcm_params* p, bool zero_weights) {
+  if (zero_weights) return kFcm;
+  return ring_params(p) ? kRing : kGather;
+}
+
+int occupancy_of(int kind, int C, int nw, bool m2, bool step) {
+  if (kind == kFcm) return fcm_occupancy(C, m2, step);
+  if (kind == kRing) return ring_occupancy(C, m2, step);
+  return gather_occupancy(C, nw, m2, step);
+}
+
+// Work items in flight per work group.
+int items_per_group(int kind, int nw) { return kind == kGather ? nw : 1; }
+
+// Offsets of the general neighbourhood (eq (9) up to the reach of V), sorted
+// by ring (Chebyshev shell, or squared distance with PIFCM_SHELL_SQDIST) with
+// their eq (7) weights, and the ring weights of eq (10), uploaded once per
+// (V, flags, h).
+pifcm_status prepare_ring(pifcm_ctx* ctx, const pifcm_params* p) {
+  const int fl = p->flags & (PIFCM_SHELL_SQDIST | PIFCM_Q2_SQDIST);
+  int hb;
+  std::memcpy(&hb, &p->h, sizeof hb);
+  if (ctx->ring_tab.p && ctx->ring_key[0] == p->V && ctx->ring_key[1] == fl && ctx->ring_key[2] == hb)
+    return PIFCM_OK;
+  const bool sq = fl & PIFCM_SHELL_SQDIST;
+  int reach = p->V;
+  if (sq) {
+    reach = 0;
+    while ((reach + 1) * (reach + 1) <= p->V) ++reach;
+  }
+  std::vector<RingOff> offs;
+  for (int r = 1; r <= p->V; ++r)
+    for (int dz = -reach; dz <= reach; ++dz)
+      for (int dy = -reach; dy <= reach; ++dy)
+        for (int dx = -reach; dx <= reach; ++dx) {
+          const int s2 = dx * dx + dy * dy + dz * dz;
+          if (s2 == 0) continue;
+          const int ring = sq ? s2 : std::max(std::abs(dx), std::max(std::abs(dy), std::abs(dz)));
+          if (ring != r) continue;
+          RingOff o{};
+          o.dx = (int16_t)dx;
+          o.dy = (int16_t)dy;
+          o.dz = (int16_t)dz;
+          o.ring = (int16_t)r;
+          o.q2 = (fl & PIFCM_Q2_SQDIST) ? (float)s2 : (float)(s2 * s2);
+          offs.push_back(o);
+        }
+  double total = 0.0;
+  for (int r = 1; r <= p->V; ++r) total += std::exp(-(double)(r - 1) / (double)p->h);
+  for (int r = 0; r <= kMaxRings; ++r)
+    ctx->ring_W[r] = (r >= 1 && r <= p->V) ? (float)(std::exp(-(double)(r - 1) / (double)p->h) / total) : 0.f;
+  TRY(ensure(ctx, ctx->ring_tab, offs.size() * sizeof(RingOff), "neighbourhood table"));
+  HIPCHK(hipMemcpyAsync(ctx->ring_tab.p, offs.data(), offs.size() * sizeof(RingOff), hipMemcpyHostToDevice,
+                        ctx->s));
+  HIPCHK(hipStreamSynchronize(ctx->s));
+  ctx->ring_n = (int)offs.size();
+  ctx->ring_key[0] = p->V;
+  ctx->ring_key[1] = fl;
+  ctx->ring_key[2] = hb;
+  ++ctx->ring_gen;
+  return PIFCM_OK;
+}
+
 // One iteration (step) or the objective-only pass: the tile kernel, then the
 // per-pair finalise that adds the tile sums and advances the state.
-hipError_t launch_step(int C, const LaunchArgs& a, int grid, int nw, bool m2, bool fcm, bool step,
+hipError_t launch_step(int C, const LaunchArgs& a, int grid, int nw, bool m2, int kind, bool step,
                        hipStream_t s) {
-  hipError_t e = fcm ? launch_fcm(C, a, grid, m2, step, s) : launch_gather(C, a, grid, nw, m2, step, s);
+  hipError_t e = kind == kFcm    ? launch_fcm(C, a, grid, m2, step, s)
+                 : kind == kRing ? launch_ring(C, a, grid, m2, step, s)
+                                 : launch_gather(C, a, grid, nw, m2, step, s);
   if (e != hipSuccess) return e;
   return launch_finalize(C, a, a.nvol * a.P, step, s);
 }
 
-LaunchArgs make_args(const VolDev* vols_dev, const PairDev* pairs_dev, const std::vector<VolDev>& vh,
-                     int nvol, int P, bool fcm, const pifcm_params* p) {
+LaunchArgs make_args(const pifcm_ctx* ctx, const VolDev* vols_dev, const PairDev* pairs_dev,
+                     const std::vector<VolDev>& vh, int nvol, int P, int kind,
+                     const pifcm_params* p) {
   LaunchArgs a;
   std::memset(&a, 0, sizeof a);
   a.vols = vols_dev;
@@ -298,11 +381,17 @@ LaunchArgs make_args(const VolDev* vols_dev, const PairDev* pairs_dev, const std
   a.P = P;
   a.q2_sqdist = (p->flags & PIFCM_Q2_SQDIST) ? 1 : 0;
   a.m = p->m;
-  a.use_1d = fcm ? 1 : 0;
+  a.use_1d = kind != kGather ? 1 : 0;
+  if (kind == kRing) {
+    a.ring = (const RingOff*)ctx->ring_tab.p;
+    a.nring = ctx->ring_n;
+    a.pad1 = ctx->ring_gen;  // part of the graph cache key
+    for (int r = 0; r <= kMaxRings; ++r) a.W[r] = ctx->ring_W[r];
+  }
   int acc = 0;
   for (int b = 0; b < nvol; ++b) {
     a.item_begin[b] = acc;
-    acc += P * (fcm ? vh[b].tiles1d : vh[b].tiles);
+    acc += P * (a.use_1d ? vh[b].tiles1d : vh[b].tiles);
   }
   a.item_begin[nvol] = acc;
   a.nitems = acc;
@@ -356,7 +445,7 @@ void pifcm_destroy(pifcm_ctx* ctx) {
   if (ctx->graph.graph) (void)hipGraphDestroy(ctx->graph.graph);
   for (DevBuf* b : {&ctx->invg, &ctx->ubuf, &ctx->partials, &ctx->states, &ctx->jhist, &ctx->tvol,
                     &ctx->tpair, &ctx->flags, &ctx->adj_ck, &ctx->adj_seg, &ctx->adj_bar,
-                    &ctx->adj_pq, &ctx->adj_misc, &ctx->tune_u0, &ctx->tune_state})
+                    &ctx->adj_pq, &ctx->adj_misc, &ctx->tune_u0, &ctx->tune_state, &ctx->ring_tab})
     if (b->p) (void)hipFree(b->p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
@@ -403,7 +492,7 @@ pifcm_status pifcm_workspace_bytes(pifcm_ctx* ctx, int64_t* device_bytes, int64_
   for (const DevBuf* b : {&ctx->invg, &ctx->ubuf, &ctx->partials, &ctx->states, &ctx->jhist,
                           &ctx->tvol, &ctx->tpair, &ctx->flags, &ctx->adj_ck, &ctx->adj_seg,
                           &ctx->adj_bar, &ctx->adj_pq, &ctx->adj_misc, &ctx->tune_u0,
-                          &ctx->tune_state})
+                          &ctx->tune_state, &ctx->ring_tab})
     d += (int64_t)b->cap;
   if (device_bytes) *device_bytes = d;
   if (pinned_bytes) *pinned_bytes = (int64_t)ctx->pinned_cap;
@@ -447,8 +536,9 @@ pifcm_status solve_impl(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_par
                         int32_t* iters_out, double* J_hist_out) {
   const int C = p->C;
   const bool m2 = p->m == 2.0f;
-  const bool fcm = lambda == 0.0f && xi == 0.0f;
+  const int kind = kind_of(p, lambda == 0.0f && xi == 0.0f);
   const size_t N = nvox(*vol);
+  if (kind == kRing) TRY(prepare_ring(ctx, p));
   std::vector<size_t> off;
   const float* u0s[1] = {U_in};
   TRY(prepare_volumes(ctx, vol, 1, C, u0s, off));
@@ -481,15 +571,15 @@ pifcm_status solve_impl(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_par
                         hipMemcpyHostToDevice, ctx->s));
   if (!U_in) HIPCHK(launch_init_u(C, vol->x, N, st_dev, p->m, m2, ubuf, ctx->s));
 
-  LaunchArgs a = make_args((const VolDev*)ctx->tvol.p, (const PairDev*)ctx->tpair.p, vh, 1, 1, fcm, p);
-  const int occ = fcm ? fcm_occupancy(C, m2, true) : gather_occupancy(C, ts.nw, m2, true);
-  const int grid = grid_for(ctx, a.nitems, occ, fcm ? 1 : ts.nw);
+  LaunchArgs a = make_args(ctx, (const VolDev*)ctx->tvol.p, (const PairDev*)ctx->tpair.p, vh, 1, 1, kind, p);
+  const int occ = occupancy_of(kind, C, ts.nw, m2, true);
+  const int grid = grid_for(ctx, a.nitems, occ, items_per_group(kind, ts.nw));
   int t = 0;
   SolveState* hst = (SolveState*)pin;
   TRY(timing_begin(ctx));
   while (t < p->max_iter) {
     const int k = p->eps > 0.f ? std::min(kChunk, p->max_iter - t) : p->max_iter - t;
-    for (int i = 0; i < k; ++i) HIPCHK(launch_step(C, a, grid, ts.nw, m2, fcm, true, ctx->s));
+    for (int i = 0; i < k; ++i) HIPCHK(launch_step(C, a, grid, ts.nw, m2, kind, true, ctx->s));
     t += k;
     if (p->eps > 0.f && t < p->max_iter) {
       HIPCHK(hipMemcpyAsync(hst, st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, ctx->s));
@@ -500,9 +590,9 @@ pifcm_status solve_impl(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_par
   TRY(timing_end(ctx));
   // Objective of the final state (the fitness).
   LaunchArgs ae = a;
-  const int occe = fcm ? fcm_occupancy(C, m2, false) : gather_occupancy(C, ts.nw, m2, false);
-  HIPCHK(launch_step(C, ae, grid_for(ctx, a.nitems, occe, fcm ? 1 : ts.nw), ts.nw, m2, fcm, false,
-                     ctx->s));
+  const int occe = occupancy_of(kind, C, ts.nw, m2, false);
+  HIPCHK(launch_step(C, ae, grid_for(ctx, a.nitems, occe, items_per_group(kind, ts.nw)), ts.nw, m2,
+                     kind, false, ctx->s));
   HIPCHK(hipMemcpyAsync(hst, st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, ctx->s));
   HIPCHK(hipStreamSynchronize(ctx->s));
   const int T = hst->iter;
@@ -670,13 +760,15 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
   HIPCHK(hipMemcpyAsync(ctx->tvol.p, hv, B * sizeof(VolDev), hipMemcpyHostToDevice, ctx->s));
 
   // lambda = xi = 0 for every particle: plain FCM kernels.
-  bool fcm = true;
-  for (long k = 0; k < 2L * B * P; ++k) fcm = fcm && particles[k] == 0.0f;
+  bool zero = true;
+  for (long k = 0; k < 2L * B * P; ++k) zero = zero && particles[k] == 0.0f;
+  const int kind = kind_of(p, zero);
+  if (kind == kRing) TRY(prepare_ring(ctx, p));
   const VolDev* vdev = (const VolDev*)ctx->tvol.p;
   const PairDev* pdev = (const PairDev*)ctx->tpair.p;
-  const int occ = fcm ? fcm_occupancy(C, m2, true) : gather_occupancy(C, ts0.nw, m2, true);
-  const int occe = fcm ? fcm_occupancy(C, m2, false) : gather_occupancy(C, ts0.nw, m2, false);
-  const int ipg = fcm ? 1 : ts0.nw;  // items in flight per work group
+  const int occ = occupancy_of(kind, C, ts0.nw, m2, true);
+  const int occe = occupancy_of(kind, C, ts0.nw, m2, false);
+  const int ipg = items_per_group(kind, ts0.nw);
 
   int64_t launches = 0;
   auto all_stopped = [&](bool& done) -> pifcm_status {
@@ -688,13 +780,13 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
   };
 
   if (mode == PIFCM_SWARM_BATCHED) {
-    LaunchArgs a = make_args(vdev, pdev, vh, B, P, fcm, p);
+    LaunchArgs a = make_args(ctx, vdev, pdev, vh, B, P, kind, p);
     const int grid = grid_for(ctx, a.nitems, occ, ipg);
     const int chunk = p->eps > 0.f ? std::min(kChunk, std::max(1, p->max_iter)) : std::max(1, p->max_iter);
     // Capture `chunk` fused launches once; replay until every pair stops.
     std::vector<char> key(sizeof(LaunchArgs) + 5 * sizeof(int));
     std::memcpy(key.data(), &a, sizeof a);
-    const int extra[5] = {grid, ts0.nw, C * 2 + (int)m2, (int)fcm, chunk};
+    const int extra[5] = {grid, ts0.nw, C * 2 + (int)m2, kind, chunk};
     std::memcpy(key.data() + sizeof a, extra, sizeof extra);
     if (ctx->graph.key != key || !ctx->graph.exec) {
       if (ctx->graph.exec) HIPCHK(hipGraphExecDestroy(ctx->graph.exec));
@@ -704,7 +796,7 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
       ctx->graph.key.clear();
       HIPCHK(hipStreamBeginCapture(ctx->s, hipStreamCaptureModeThreadLocal));
       for (int i = 0; i < chunk; ++i) {
-        hipError_t e = launch_step(C, a, grid, ts0.nw, m2, fcm, true, ctx->s);
+        hipError_t e = launch_step(C, a, grid, ts0.nw, m2, kind, true, ctx->s);
         if (e != hipSuccess) {
           hipGraph_t g = nullptr;
           (void)hipStreamEndCapture(ctx->s, &g);
@@ -729,7 +821,7 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
     }
     TRY(timing_end(ctx));
     launches = t;
-    HIPCHK(launch_step(C, a, grid_for(ctx, a.nitems, occe, ipg), ts0.nw, m2, fcm, false, ctx->s));
+    HIPCHK(launch_step(C, a, grid_for(ctx, a.nitems, occe, ipg), ts0.nw, m2, kind, false, ctx->s));
   } else {
     // One launch per (volume, particle) per iteration.
     std::vector<LaunchArgs> args(npairs);
@@ -738,7 +830,7 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
       std::vector<VolDev> one{vh[b]};
       for (int q = 0; q < P; ++q) {
         const size_t k = (size_t)b * P + q;
-        args[k] = make_args(vdev + b, pdev + k, one, 1, 1, fcm, p);
+        args[k] = make_args(ctx, vdev + b, pdev + k, one, 1, 1, kind, p);
         grids[k] = grid_for(ctx, args[k].nitems, occ, ipg);
         gride[k] = grid_for(ctx, args[k].nitems, occe, ipg);
       }
@@ -749,7 +841,7 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
       const int k = p->eps > 0.f ? std::min(kChunk, p->max_iter - t) : p->max_iter - t;
       for (int i = 0; i < k; ++i)
         for (size_t q = 0; q < npairs; ++q)
-          HIPCHK(launch_step(C, args[q], grids[q], ts0.nw, m2, fcm, true, ctx->s));
+          HIPCHK(launch_step(C, args[q], grids[q], ts0.nw, m2, kind, true, ctx->s));
       t += k;
       if (t < p->max_iter) {
         bool done = false;
@@ -760,7 +852,7 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
     TRY(timing_end(ctx));
     launches = (int64_t)t * (int64_t)npairs;
     for (size_t q = 0; q < npairs; ++q)
-      HIPCHK(launch_step(C, args[q], gride[q], ts0.nw, m2, fcm, false, ctx->s));
+      HIPCHK(launch_step(C, args[q], gride[q], ts0.nw, m2, kind, false, ctx->s));
   }
   HIPCHK(hipMemcpyAsync(hs, st_dev, npairs * sizeof(SolveState), hipMemcpyDeviceToHost, ctx->s));
   HIPCHK(hipStreamSynchronize(ctx->s));
@@ -784,6 +876,8 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
   ctx->err.clear();
   TRY(check_volume(ctx, vol));
   TRY(check_params(ctx, p));
+  if (ring_params(p))
+    return fail(ctx, PIFCM_E_UNSUPPORTED, "the adjoint is built for the 3x3x3 neighbourhood (V = 1)");
   if (!(std::fabs(lambda) <= kMaxWeight) || !(std::fabs(xi) <= kMaxWeight))
     return fail(ctx, PIFCM_E_INVALID, "lambda and xi must be finite with magnitude <= %g", kMaxWeight);
   if (!centres0 || !U0 || !dJ_dlambda || !dJ_dxi || !dJ_dcentres)
@@ -796,8 +890,9 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
     return fail(ctx, PIFCM_E_INVALID, "ckpt_every = %d outside [1, K = %d]", ckpt_every, K);
   const int C = p->C, S = ckpt_every;
   const bool m2 = p->m == 2.0f;
-  const bool fcm = lambda == 0.0f && xi == 0.0f;
+  const int kind = kind_of(p, lambda == 0.0f && xi == 0.0f);
   const size_t N = nvox(*vol);
+  if (kind == kRing) TRY(prepare_ring(ctx, p));
   const size_t UB = N * C * sizeof(float);
   TRY(begin(ctx));
   std::vector<size_t> off;
@@ -860,18 +955,18 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
                         hipMemcpyHostToDevice, ctx->s));
   HIPCHK(hipMemcpyAsync(c_hist, pin + sizeof(SolveState) + sizeof(PairDev) + sizeof(VolDev),
                         C * sizeof(float), hipMemcpyHostToDevice, ctx->s));
-  LaunchArgs a = make_args((const VolDev*)ctx->tvol.p, tp, vh, 1, 1, fcm, p);
-  const int occ = fcm ? fcm_occupancy(C, m2, true) : gather_occupancy(C, ts.nw, m2, true);
-  const int grid = grid_for(ctx, a.nitems, occ, fcm ? 1 : ts.nw);
-  const int occe = fcm ? fcm_occupancy(C, m2, false) : gather_occupancy(C, ts.nw, m2, false);
-  const int gride = grid_for(ctx, a.nitems, occe, fcm ? 1 : ts.nw);
+  LaunchArgs a = make_args(ctx, (const VolDev*)ctx->tvol.p, tp, vh, 1, 1, kind, p);
+  const int occ = occupancy_of(kind, C, ts.nw, m2, true);
+  const int grid = grid_for(ctx, a.nitems, occ, items_per_group(kind, ts.nw));
+  const int occe = occupancy_of(kind, C, ts.nw, m2, false);
+  const int gride = grid_for(ctx, a.nitems, occe, items_per_group(kind, ts.nw));
   auto ckpt = [&](int t) -> float* { return (float*)((char*)ctx->adj_ck.p + (size_t)(t / S - 1) * UB); };
   for (int t = 0; t < K; ++t) {
-    HIPCHK(launch_step(C, a, grid, ts.nw, m2, fcm, true, ctx->s));
+    HIPCHK(launch_step(C, a, grid, ts.nw, m2, kind, true, ctx->s));
     if ((t + 1) % S == 0 && t + 1 <= K - 1)
       HIPCHK(hipMemcpyAsync(ckpt(t + 1), u_out_of(pr, t + 1), UB, hipMemcpyDeviceToDevice, ctx->s));
   }
-  HIPCHK(launch_step(C, a, gride, ts.nw, m2, fcm, false, ctx->s));
+  HIPCHK(launch_step(C, a, gride, ts.nw, m2, kind, false, ctx->s));
   SolveState* hst = (SolveState*)pin;
   float* hc = (float*)(pin + (size_t)(S + 2) * (sizeof(SolveState) + sizeof(PairDev)) + sizeof(VolDev));
   HIPCHK(hipMemcpyAsync(hst, st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, ctx->s));
@@ -907,7 +1002,7 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
   // Recomputed states of the current segment: seg[i] = U^(t0 + i).
   std::vector<const float*> seg(S, nullptr);
   int seg_t0 = -1;
-  LaunchArgs a1 = make_args((const VolDev*)ctx->tvol.p, tp + 1, vh, 1, 1, fcm, p);
+  LaunchArgs a1 = make_args(ctx, (const VolDev*)ctx->tvol.p, tp + 1, vh, 1, 1, kind, p);
   for (int t = K - 1; t >= 0; --t) {
     const int t0 = (t / S) * S;
     if (t0 != seg_t0) {
@@ -930,7 +1025,7 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
         std::memcpy(slot + sizeof(SolveState), &q, sizeof q);
         HIPCHK(hipMemcpyAsync(st_dev + 1, slot, sizeof s1, hipMemcpyHostToDevice, ctx->s));
         HIPCHK(hipMemcpyAsync(tp + 1, slot + sizeof(SolveState), sizeof q, hipMemcpyHostToDevice, ctx->s));
-        HIPCHK(launch_step(C, a1, grid, ts.nw, m2, fcm, true, ctx->s));
+        HIPCHK(launch_step(C, a1, grid, ts.nw, m2, kind, true, ctx->s));
         seg[i] = q.Ua;
       }
       HIPCHK(hipStreamSynchronize(ctx->s));  // pinned slots are reused by the next segment
@@ -964,6 +1059,13 @@ pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
   if (!vols || B < 1 || B > kMaxBatchVols) return fail(ctx, PIFCM_E_INVALID, "B = %d outside [1, %d]", B, kMaxBatchVols);
   if (P < 1 || (long)B * P > kMaxPairs) return fail(ctx, PIFCM_E_INVALID, "P = %d out of range", P);
   TRY(check_params(ctx, p));
+  if (ring_params(p)) {
+    if (best_out && best_len > 0) {
+      std::strncpy(best_out, "general neighbourhood: fixed decomposition, nothing timed", (size_t)best_len - 1);
+      best_out[best_len - 1] = 0;
+    }
+    return PIFCM_OK;
+  }
   for (int b = 0; b < B; ++b) TRY(check_volume(ctx, &vols[b]));
   const int C = p->C;
   const bool m2 = p->m == 2.0f;

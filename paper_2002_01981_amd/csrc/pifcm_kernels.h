@@ -16,6 +16,9 @@ hipError_t launch_gather(int C, const LaunchArgs& a, int grid, int ty, bool m2, 
 hipError_t launch_finalize(int C, const LaunchArgs& a, int npairs, bool step, hipStream_t s);
 // Pointwise FCM step / objective (lambda = xi = 0).
 hipError_t launch_fcm(int C, const LaunchArgs& a, int grid, bool m2, bool step, hipStream_t s);
+// IFCM step / objective for general neighbourhoods (a.ring, a.W).
+hipError_t launch_ring(int C, const LaunchArgs& a, int grid, bool m2, bool step, hipStream_t s);
+int ring_occupancy(int C, bool m2, bool step);
 hipError_t launch_init_u(int C, const float* x, size_t N, const SolveState* st, float m, bool m2,
                          float* U, hipStream_t s);
 hipError_t launch_invariants(const float* x, float* invg, int nx, int ny, int nz, int* flag,

@@ -270,7 +270,7 @@ def test_error_paths(ctx):
 
     assert status(lambda: ctx.ifcm_solve(x, _P(C=1), 0.3, 0.3, c0[:1])) == PIFCM_E_INVALID
     assert status(lambda: ctx.ifcm_solve(x, _P(m=1.0), 0.3, 0.3, c0)) == PIFCM_E_INVALID
-    assert status(lambda: ctx.ifcm_solve(x, _P(V=2), 0.3, 0.3, c0)) == PIFCM_E_UNSUPPORTED
+    assert status(lambda: ctx.ifcm_solve(x, _P(V=4), 0.3, 0.3, c0)) == PIFCM_E_UNSUPPORTED
     assert status(lambda: ctx.ifcm_solve(x, _P(), float("nan"), 0.3, c0)) == PIFCM_E_INVALID
     bad = x.clone()
     bad[1, 2, 3] = float("nan")
