@@ -103,6 +103,36 @@ def adjoint_leg(Context, Params):
                 J=g["J"], dJ_dlambda=g["dlam"], dJ_dxi=g["dxi"])
 
 
+def ring_leg(Context, Params, vol_raw, dims):
+    """The general-neighbourhood kernel (two Chebyshev rings, 5x5x5, h = 1)
+    on the largest volume of the batch: 8 particles x 5 iterations, batched,
+    timed by the library's HIP events."""
+    import numpy as np
+    import torch
+    import synth
+    ctx = Context(0)
+    x = ctx.pifcm_normalize(torch.from_numpy(vol_raw).cuda())
+    c0, U0, _ = ctx.pifcm_fcm_init(x, Params(C=4, m=2.0, eps=0.0, max_iter=10))
+    P, T = 8, 5
+    parts = synth.uniform_particles(104, P)
+    p = Params(C=4, m=2.0, V=2, h=1.0, eps=0.0, max_iter=T)
+    ctx.swarm_evaluate([x], p, parts, c0[None], [U0])
+    torch.cuda.synchronize()
+    ctx.pifcm_get_timing(reset=True)
+    ctx.pifcm_set_timing(True)
+    ctx.swarm_evaluate([x], p, parts, c0[None], [U0])
+    ctx.pifcm_set_timing(False)
+    ms, launches = ctx.pifcm_get_timing(reset=True)
+    ctx.close()
+    n = int(np.prod(dims))
+    per_launch = n * P * (8 * 4 + 4)
+    avg = ms / max(launches, 1)
+    return dict(kernel="k_ifcm_ring<4, m=2, step>", neighbourhood="5x5x5, 2 rings, h=1",
+                volume_zyx=list(dims), particles=P, iterations=T, avg_launch_us=round(avg * 1e3, 2),
+                value=n * 4 * P / (avg * 1e-3), unit="voxel-cluster-iters/s",
+                algorithmic_GBps=round(per_launch / (avg * 1e-3) / 1e9, 1))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +145,7 @@ def main():
                     help="length of the oracle's timed sample")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
+    ap.add_argument("--no-ring", action="store_true", help="skip the general-neighbourhood leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device copy of MIB MiB a few times (counter scaling)")
     args = ap.parse_args()
@@ -230,6 +261,12 @@ def main():
                      bit_identical_to_batched=same)
         log(f"plain: {(tp1 - tp0) * 1e3:.1f} ms/step, identical={same}")
 
+    ring = None
+    if not args.no_ring:
+        b = int(np.argmax(nvox))
+        ring = ring_leg(Context, Params, vols[b][0], dims[b])
+        log(f"ring kernel: {ring['avg_launch_us']} us per launch")
+
     adjoint = None
     if not args.no_adjoint:
         adjoint = adjoint_leg(Context, Params)
@@ -269,6 +306,7 @@ def main():
         "roofline": roofline,
         "tune": tune,
         "plain": plain,
+        "ring": ring,
         "adjoint": adjoint,
         "cpu_baseline": cpu,
     }

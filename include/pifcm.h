@@ -116,6 +116,20 @@ pifcm_status ifcm_solve(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_par
                         float* U_out, float* centres_out, uint8_t* labels_out, double* J_out,
                         int32_t* iters_out, double* J_hist_out);
 
+/* Slab mode of ifcm_solve -- Algorithm 1 step 1 segments one slice z of the
+ * volume with its 3D neighbours: only the planes [zbeg, zend) (e.g. [z,
+ * z + 1)) are iterated; the memberships of every other plane stay those of
+ * U_in (required) and enter the neighbourhood sums as fixed context.  The
+ * centres (eq (3)) and J (eq (1)) are sums over the planes iterated.
+ * U_out (device [N][C]) receives the whole volume (context planes copied
+ * from U_in), labels_out (device [N] or NULL) its labels; other arguments
+ * as ifcm_solve.  0 <= zbeg < zend <= nz. */
+pifcm_status ifcm_solve_slab(pifcm_ctx* ctx, const pifcm_volume* vol, int32_t zbeg, int32_t zend,
+                             const pifcm_params* p, float lambda, float xi, const float* centres_in,
+                             const float* U_in, float* U_out, float* centres_out,
+                             uint8_t* labels_out, double* J_out, int32_t* iters_out,
+                             double* J_hist_out);
+
 /* Initial state of Algorithm 1 step 2: plain FCM (lambda = xi = 0) from
  * evenly spaced centres c_j = (j + 1/2) / C, then the centres sorted
  * ascending with the membership columns permuted alike.  The paper seeds
@@ -188,6 +202,36 @@ pifcm_status pifcm_pso(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, cons
                        const double* r2, double w, double c1, double c2, const float* centres0,
                        const float* const* U0, int32_t mode, double* best_pos, double* best_fit,
                        double* fit_hist, double* pos_hist);
+
+/* The interleaved reading of the swarm schedule (Algorithm 2, step 11):
+ * every particle carries its own IFCM state.  Particle q of volume b starts
+ * from (centres0[b], U0[b]); in generation g it runs `steps` IFCM iterations
+ * (no stop rule; p->eps and p->max_iter are not used) at its current
+ * (lambda, xi) from the state it reached in generation g - 1, its fitness is
+ * J of eq (1) at the new state, and the swarm then moves as in pifcm_pso
+ * (same update, same random-number arguments and outputs).  U_best_out
+ * (host array [B] of device [N_b][C], may be NULL) and centres_best_out
+ * (host [B][C], may be NULL) receive, per volume, the final state of the
+ * particle whose personal best is the global best.  The library holds one
+ * membership buffer per (volume, particle) for the states. */
+pifcm_status pifcm_pso_interleaved(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
+                                   const pifcm_params* p, int32_t P, int32_t G, int32_t steps,
+                                   const double* x0, const double* v0, const double* r1,
+                                   const double* r2, double w, double c1, double c2,
+                                   const float* centres0, const float* const* U0, int32_t mode,
+                                   double* best_pos, double* best_fit, double* fit_hist,
+                                   double* pos_hist, float* const* U_best_out,
+                                   float* centres_best_out);
+
+/* Segmentation quality against a reference: confusion counts of labels
+ * (device [n] uint8, cluster indices 0..C-1, e.g. from ifcm_solve) against
+ * truth (device [n] uint8, classes 0..K-1): counts_out (host [C][K] int64)
+ * [j][k] = number of voxels labelled j whose class is k.  With centres sorted
+ * ascending and classes numbered by intensity, the misclassification rate
+ * of the paper's quality comparisons (section 6) is 1 - trace / n.
+ * PIFCM_E_INVALID if a label or class is out of range. */
+pifcm_status pifcm_confusion(pifcm_ctx* ctx, const uint8_t* labels, const uint8_t* truth, int64_t n,
+                             int32_t C, int32_t K, int64_t* counts_out);
 
 /* Device workspace the context holds (bytes, host outputs; either may be
  * NULL): the sum of its device buffers, which only grow, so this is also the

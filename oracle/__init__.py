@@ -56,10 +56,15 @@ def lib():
         _lib.oracle_step.argtypes = [f, i, i, i, pp, ct.c_double, ct.c_double, d, d, d, d, d, d, d]
         _lib.oracle_solve.argtypes = [f, i, i, i, pp, ct.c_double, ct.c_double, d, d, d, d, d,
                                       ct.POINTER(ct.c_int32), d]
+        _lib.oracle_solve_slab.argtypes = [f, i, i, i, i, i, pp, ct.c_double, ct.c_double, d, d,
+                                           d, d, d, ct.POINTER(ct.c_int32), d]
         _lib.oracle_fcm_init.argtypes = [f, i, i, i, pp, d, d, ct.POINTER(ct.c_int32)]
         _lib.oracle_labels.argtypes = [d, i64, i, ct.POINTER(ct.c_uint8)]
         _lib.oracle_pso.argtypes = [f, i, i, i, pp, d, d, i, i, d, d, d, d, ct.c_double,
                                     ct.c_double, ct.c_double, d, d, d, d]
+        _lib.oracle_pso_interleaved.argtypes = [f, i, i, i, pp, d, d, i, i, i, d, d, d, d,
+                                                ct.c_double, ct.c_double, ct.c_double, d, d, d,
+                                                d, d, d]
         _lib.oracle_fd_grad.argtypes = [f, i, i, i, pp, ct.c_double, ct.c_double, d, d, i,
                                         ct.c_double, d, d]
         _lib.oracle_set_threads.argtypes = [i]
@@ -152,6 +157,26 @@ def solve(x, c0, p: Params, lam, xi, U0=None, want_hist=False):
     return out
 
 
+def solve_slab(x, c0, p: Params, lam, xi, U0, zbeg, zend, want_hist=False):
+    """IFCM solve of the planes [zbeg, zend) only, the other planes' memberships
+    held at U0 (context).  Returns dict(U, c, J, iters[, J_hist])."""
+    x = _f32(x)
+    nz, ny, nx = x.shape
+    U0 = _f64(U0).reshape(-1, p.C)
+    U = np.empty_like(U0)
+    c = np.empty(p.C)
+    J = ct.c_double()
+    it = ct.c_int32()
+    hist = np.empty(max(1, p.max_iter)) if want_hist else None
+    _check(lib().oracle_solve_slab(_pf(x), nx, ny, nz, int(zbeg), int(zend), ct.byref(p.c()),
+                                   float(lam), float(xi), _pd(_f64(c0)), _pd(U0), _pd(U), _pd(c),
+                                   ct.byref(J), ct.byref(it), _pd(hist)), "solve_slab")
+    out = dict(U=U, c=c, J=J.value, iters=it.value)
+    if want_hist:
+        out["J_hist"] = hist[: it.value].copy()
+    return out
+
+
 def fcm_init(x, p: Params):
     """Initial (c0, U0): FCM from evenly spaced centres, sorted."""
     x = _f32(x)
@@ -189,6 +214,29 @@ def pso(x, c0, U0, p: Params, streams, w=0.7, c1=1.5, c2=1.5):
                             _pd(_f64(U0).reshape(-1, p.C)), P, G, _pd(x0), _pd(v0), _pd(r1),
                             _pd(r2), w, c1, c2, _pd(bp), ct.byref(bf), _pd(fh), _pd(ph)), "pso")
     return dict(best_pos=bp, best_fit=bf.value, fit_hist=fh, pos_hist=ph)
+
+
+def pso_interleaved(x, c0, U0, p: Params, streams, steps=1, w=0.7, c1=1.5, c2=1.5):
+    """Swarm whose particles carry their own IFCM state (`steps` iterations
+    per generation).  Returns dict(best_pos, best_fit, fit_hist, pos_hist,
+    U_best, c_best)."""
+    x = _f32(x)
+    nz, ny, nx = x.shape
+    x0, v0 = _f64(streams["x0"]), _f64(streams["v0"])
+    r1, r2 = _f64(streams["r1"]), _f64(streams["r2"])
+    G, P = r1.shape[0], r1.shape[1]
+    bp = np.empty(2)
+    bf = ct.c_double()
+    fh = np.empty((G, P))
+    ph = np.empty((G, P, 2))
+    Ub = np.empty((x.size, p.C))
+    cb = np.empty(p.C)
+    _check(lib().oracle_pso_interleaved(_pf(x), nx, ny, nz, ct.byref(p.c()), _pd(_f64(c0)),
+                                        _pd(_f64(U0).reshape(-1, p.C)), P, G, int(steps), _pd(x0),
+                                        _pd(v0), _pd(r1), _pd(r2), w, c1, c2, _pd(bp),
+                                        ct.byref(bf), _pd(fh), _pd(ph), _pd(Ub), _pd(cb)),
+           "pso_interleaved")
+    return dict(best_pos=bp, best_fit=bf.value, fit_hist=fh, pos_hist=ph, U_best=Ub, c_best=cb)
 
 
 def fd_grad(x, c0, U0, p: Params, lam, xi, K, step=1e-4):

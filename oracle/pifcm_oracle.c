@@ -174,10 +174,16 @@ int oracle_init_memberships(const float* x, int64_t n, const or_params* p, const
 /* One IFCM step (section 4, "step function"): from (U, c) compute H, F
  * (eqs (5)-(10)), the modified distances (eq (4)), J of the input state
  * (eq (1)), new memberships (eq (2)) and new centres (eq (3)). */
-int oracle_step(const float* x, int nx, int ny, int nz, const or_params* p, double lambda,
-                double xi, const double* U, const double* c, double* U_out, double* c_out,
-                double* J_out, double* H_out, double* F_out) {
+/* The step over the planes [zbeg, zend) only: memberships of the other
+ * planes are copied unchanged to U_out (they act as fixed context), and the
+ * centres and J are sums over the active planes (Algorithm 1, step 1:
+ * segmenting one slice with its 3D neighbours). */
+static int step_range(const float* x, int nx, int ny, int nz, int zbeg, int zend,
+                      const or_params* p, double lambda, double xi, const double* U,
+                      const double* c, double* U_out, double* c_out, double* J_out,
+                      double* H_out, double* F_out) {
   if (!params_ok(p) || !x || !U || !c || nx < 1 || ny < 1 || nz < 1) return -1;
+  if (zbeg < 0 || zend > nz || zbeg >= zend) return -1;
   const int C = p->C, V = p->V;
   const double m = p->m;
   or_offset* off = NULL;
@@ -187,8 +193,13 @@ int oracle_step(const float* x, int nx, int ny, int nz, const or_params* p, doub
   const int stride = 2 * C + 1;
   double* parts = (double*)calloc((size_t)nz * stride, sizeof(double));
 
+  if (U_out)
+    for (int z = 0; z < nz; ++z)
+      if (z < zbeg || z >= zend)
+        memcpy(U_out + (size_t)z * ny * nx * C, U + (size_t)z * ny * nx * C,
+               sizeof(double) * (size_t)ny * nx * C);
 #pragma omp parallel for schedule(static)
-  for (int z = 0; z < nz; ++z) {
+  for (int z = zbeg; z < zend; ++z) {
     double* part = parts + (size_t)z * stride; /* num[C], den[C], J */
     double gs[OR_MAX_RING], qs[OR_MAX_RING];
     int cnt[OR_MAX_RING];
@@ -253,7 +264,7 @@ int oracle_step(const float* x, int nx, int ny, int nz, const or_params* p, doub
   double J = 0.0;
   double num[OR_MAX_C], den[OR_MAX_C];
   for (int j = 0; j < C; ++j) num[j] = den[j] = 0.0;
-  for (int z = 0; z < nz; ++z) {
+  for (int z = zbeg; z < zend; ++z) {
     const double* part = parts + (size_t)z * stride;
     for (int j = 0; j < C; ++j) {
       num[j] += part[j];
@@ -269,12 +280,19 @@ int oracle_step(const float* x, int nx, int ny, int nz, const or_params* p, doub
   return 0;
 }
 
+int oracle_step(const float* x, int nx, int ny, int nz, const or_params* p, double lambda,
+                double xi, const double* U, const double* c, double* U_out, double* c_out,
+                double* J_out, double* H_out, double* F_out) {
+  return step_range(x, nx, ny, nz, 0, nz, p, lambda, xi, U, c, U_out, c_out, J_out, H_out, F_out);
+}
+
 /* The IFCM solve of Algorithm 1 step 11 (and of every fitness evaluation of
  * steps 4-9): iterate the step until the relative change of J falls to eps
  * or max_iter is reached.  The fitness is J of the final state. */
-int oracle_solve(const float* x, int nx, int ny, int nz, const or_params* p, double lambda,
-                 double xi, const double* c0, const double* U0, double* U_out, double* c_out,
-                 double* J_fit, int32_t* iters, double* J_hist) {
+static int solve_range(const float* x, int nx, int ny, int nz, int zbeg, int zend,
+                       const or_params* p, double lambda, double xi, const double* c0,
+                       const double* U0, double* U_out, double* c_out, double* J_fit,
+                       int32_t* iters, double* J_hist) {
   if (!params_ok(p) || !x || !c0 || !U_out || !c_out) return -1;
   const int C = p->C;
   const int64_t n = (int64_t)nx * ny * nz;
@@ -291,7 +309,7 @@ int oracle_solve(const float* x, int nx, int ny, int nz, const or_params* p, dou
   int t = 0;
   for (t = 1; t <= p->max_iter; ++t) {
     double J = 0.0;
-    int rc = oracle_step(x, nx, ny, nz, p, lambda, xi, Ua, ca, Ub, cb, &J, NULL, NULL);
+    int rc = step_range(x, nx, ny, nz, zbeg, zend, p, lambda, xi, Ua, ca, Ub, cb, &J, NULL, NULL);
     if (rc) {
       free(Ua);
       free(Ub);
@@ -308,7 +326,7 @@ int oracle_solve(const float* x, int nx, int ny, int nz, const or_params* p, dou
   }
   int T = t > p->max_iter ? p->max_iter : t;
   double Jf = 0.0;
-  oracle_step(x, nx, ny, nz, p, lambda, xi, Ua, ca, NULL, NULL, &Jf, NULL, NULL);
+  step_range(x, nx, ny, nz, zbeg, zend, p, lambda, xi, Ua, ca, NULL, NULL, &Jf, NULL, NULL);
   memcpy(U_out, Ua, sizeof(double) * (size_t)n * C);
   memcpy(c_out, ca, sizeof(double) * C);
   if (J_fit) *J_fit = Jf;
@@ -316,6 +334,24 @@ int oracle_solve(const float* x, int nx, int ny, int nz, const or_params* p, dou
   free(Ua);
   free(Ub);
   return 0;
+}
+
+int oracle_solve(const float* x, int nx, int ny, int nz, const or_params* p, double lambda,
+                 double xi, const double* c0, const double* U0, double* U_out, double* c_out,
+                 double* J_fit, int32_t* iters, double* J_hist) {
+  return solve_range(x, nx, ny, nz, 0, nz, p, lambda, xi, c0, U0, U_out, c_out, J_fit, iters,
+                     J_hist);
+}
+
+/* Slab mode: only the planes [zbeg, zend) are iterated; the memberships of
+ * the other planes stay those of U0 (required) and serve as neighbours. */
+int oracle_solve_slab(const float* x, int nx, int ny, int nz, int zbeg, int zend,
+                      const or_params* p, double lambda, double xi, const double* c0,
+                      const double* U0, double* U_out, double* c_out, double* J_fit,
+                      int32_t* iters, double* J_hist) {
+  if (!U0) return -1;
+  return solve_range(x, nx, ny, nz, zbeg, zend, p, lambda, xi, c0, U0, U_out, c_out, J_fit, iters,
+                     J_hist);
 }
 
 /* Initial centres and memberships (Algorithm 1 step 2): plain FCM from
@@ -434,6 +470,96 @@ int oracle_pso(const float* x, int nx, int ny, int nz, const or_params* p, const
   free(pb);
   free(pbf);
   free(Ut);
+  return 0;
+}
+
+/* The interleaved reading of the swarm schedule (Algorithm 2, step 11):
+ * each particle keeps its own IFCM state (U, c), starting from (U0, c0);
+ * in every generation it advances `steps` IFCM iterations at its current
+ * (lambda, xi) and its fitness is J of the state it reaches; the swarm then
+ * moves exactly as in oracle_pso.  U_best / c_best (optional) receive the
+ * state of the particle holding the global best after the last
+ * generation. */
+int oracle_pso_interleaved(const float* x, int nx, int ny, int nz, const or_params* p,
+                           const double* c0, const double* U0, int P, int G, int steps,
+                           const double* x0, const double* v0, const double* r1, const double* r2,
+                           double w, double c1, double c2, double* best_pos, double* best_fit,
+                           double* fit_hist, double* pos_hist, double* U_best, double* c_best) {
+  if (!params_ok(p) || P < 1 || G < 1 || steps < 1 || !x0 || !v0 || !r1 || !r2 || !U0 || !c0)
+    return -1;
+  const int C = p->C;
+  const int64_t n = (int64_t)nx * ny * nz;
+  or_params q = *p;
+  q.eps = 0.0;
+  q.max_iter = steps;
+  double* U = (double*)malloc(sizeof(double) * (size_t)P * n * C); /* state of each particle */
+  double* cs = (double*)malloc(sizeof(double) * (size_t)P * C);
+  double* Ut = (double*)malloc(sizeof(double) * (size_t)n * C);
+  double* pos = (double*)malloc(sizeof(double) * P * 2);
+  double* vel = (double*)malloc(sizeof(double) * P * 2);
+  double* pb = (double*)malloc(sizeof(double) * P * 2);
+  double* pbf = (double*)malloc(sizeof(double) * P);
+  double gb[2] = {0.0, 0.0}, gbf = 0.0;
+  int gq = 0;
+  for (int k = 0; k < P; ++k) {
+    memcpy(U + (size_t)k * n * C, U0, sizeof(double) * (size_t)n * C);
+    memcpy(cs + (size_t)k * C, c0, sizeof(double) * C);
+  }
+  memcpy(pos, x0, sizeof(double) * P * 2);
+  memcpy(vel, v0, sizeof(double) * P * 2);
+  for (int g = 0; g < G; ++g) {
+    for (int k = 0; k < P; ++k) {
+      double ct[OR_MAX_C], f = 0.0;
+      int32_t it = 0;
+      oracle_solve(x, nx, ny, nz, &q, pos[2 * k], pos[2 * k + 1], cs + (size_t)k * C,
+                   U + (size_t)k * n * C, Ut, ct, &f, &it, NULL);
+      memcpy(U + (size_t)k * n * C, Ut, sizeof(double) * (size_t)n * C);
+      memcpy(cs + (size_t)k * C, ct, sizeof(double) * C);
+      if (fit_hist) fit_hist[(size_t)g * P + k] = f;
+      if (pos_hist) {
+        pos_hist[((size_t)g * P + k) * 2] = pos[2 * k];
+        pos_hist[((size_t)g * P + k) * 2 + 1] = pos[2 * k + 1];
+      }
+      if (g == 0 || f < pbf[k]) {
+        pbf[k] = f;
+        pb[2 * k] = pos[2 * k];
+        pb[2 * k + 1] = pos[2 * k + 1];
+      }
+    }
+    for (int k = 0; k < P; ++k) {
+      if (k == 0 || pbf[k] < gbf) {
+        gbf = pbf[k];
+        gb[0] = pb[2 * k];
+        gb[1] = pb[2 * k + 1];
+        gq = k;
+      }
+    }
+    if (g + 1 == G) break;
+    for (int k = 0; k < P; ++k) {
+      for (int d = 0; d < 2; ++d) {
+        const size_t sidx = ((size_t)g * P + k) * 2 + d;
+        double v = w * vel[2 * k + d] + c1 * r1[sidx] * (pb[2 * k + d] - pos[2 * k + d]) +
+                   c2 * r2[sidx] * (gb[d] - pos[2 * k + d]);
+        double np = pos[2 * k + d] + v;
+        vel[2 * k + d] = v;
+        pos[2 * k + d] = np < 0.0 ? 0.0 : (np > 1.0 ? 1.0 : np);
+      }
+    }
+  }
+  if (best_pos) {
+    best_pos[0] = gb[0];
+    best_pos[1] = gb[1];
+  }
+  if (best_fit) *best_fit = gbf;
+  if (U_best) memcpy(U_best, U + (size_t)gq * n * C, sizeof(double) * (size_t)n * C);
+  if (c_best) memcpy(c_best, cs + (size_t)gq * C, sizeof(double) * C);
+  free(U);
+  free(cs);
+  free(Ut);
+  free(pos);
+  free(vel);
+  free(pb);
+  free(pbf);
   return 0;
 }
 

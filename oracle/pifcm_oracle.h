@@ -31,10 +31,14 @@
  *                          sum-to-one of eq (2), the m = 2 identity
  *   oracle_solve ......... FCM descent, constant image, axis flips,
  *                          transposes and centre permutations
+ *   oracle_solve_slab .... whole-volume slab equals oracle_solve; one-step
+ *                          brute force of the active planes; fixed context
  *   oracle_fcm_init ...... sorted centres; equals solve-then-sort
  *   oracle_labels ........ numpy argmax (first maximum)
  *   oracle_pso ........... one hand-derived generation; frozen swarm;
  *                          re-evaluated fitness; pbest monotonicity
+ *   oracle_pso_interleaved frozen swarm equals one long solve; steps =
+ *                          max_iter with one generation equals oracle_pso
  *   oracle_fd_grad ....... closed-form derivative at K = 0; step-size
  *                          agreement h vs h/2
  */
@@ -76,6 +80,11 @@ int oracle_solve(const float* x, int nx, int ny, int nz, const or_params* p, dou
                  double xi, const double* c0, const double* U0, double* U_out, double* c_out,
                  double* J_fit, int32_t* iters, double* J_hist);
 
+int oracle_solve_slab(const float* x, int nx, int ny, int nz, int zbeg, int zend,
+                      const or_params* p, double lambda, double xi, const double* c0,
+                      const double* U0, double* U_out, double* c_out, double* J_fit,
+                      int32_t* iters, double* J_hist);
+
 int oracle_fcm_init(const float* x, int nx, int ny, int nz, const or_params* p, double* U_out,
                     double* c_out, int32_t* iters);
 
@@ -85,6 +94,12 @@ int oracle_pso(const float* x, int nx, int ny, int nz, const or_params* p, const
                const double* U0, int P, int G, const double* x0, const double* v0,
                const double* r1, const double* r2, double w, double c1, double c2,
                double* best_pos, double* best_fit, double* fit_hist, double* pos_hist);
+
+int oracle_pso_interleaved(const float* x, int nx, int ny, int nz, const or_params* p,
+                           const double* c0, const double* U0, int P, int G, int steps,
+                           const double* x0, const double* v0, const double* r1, const double* r2,
+                           double w, double c1, double c2, double* best_pos, double* best_fit,
+                           double* fit_hist, double* pos_hist, double* U_best, double* c_best);
 
 int oracle_fd_grad(const float* x, int nx, int ny, int nz, const or_params* p, double lambda,
                    double xi, const double* c0, const double* U0, int K, double step,

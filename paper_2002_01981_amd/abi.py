@@ -98,6 +98,9 @@ def load_library(path=LIB_PATH):
     lib.ifcm_solve.argtypes = [vp, P(_Volume), P(_Params), f32, f32, P(f32), vp, vp, P(f32), vp,
                                P(f64), P(i32), P(f64)]
     lib.ifcm_solve.restype = st
+    lib.ifcm_solve_slab.argtypes = [vp, P(_Volume), i32, i32, P(_Params), f32, f32, P(f32), vp, vp,
+                                    P(f32), vp, P(f64), P(i32), P(f64)]
+    lib.ifcm_solve_slab.restype = st
     lib.pifcm_fcm_init.argtypes = [vp, P(_Volume), P(_Params), vp, P(f32), P(i32)]
     lib.pifcm_fcm_init.restype = st
     lib.swarm_evaluate.argtypes = [vp, P(_Volume), i32, P(_Params), P(f32), i32, P(f32), P(vp),
@@ -112,6 +115,12 @@ def load_library(path=LIB_PATH):
                               P(f64), f64, f64, f64, P(f32), P(vp), i32, P(f64), P(f64), P(f64),
                               P(f64)]
     lib.pifcm_pso.restype = st
+    lib.pifcm_pso_interleaved.argtypes = [vp, P(_Volume), i32, P(_Params), i32, i32, i32, P(f64),
+                                          P(f64), P(f64), P(f64), f64, f64, f64, P(f32), P(vp),
+                                          i32, P(f64), P(f64), P(f64), P(f64), P(vp), P(f32)]
+    lib.pifcm_pso_interleaved.restype = st
+    lib.pifcm_confusion.argtypes = [vp, vp, vp, i64, i32, i32, P(i64)]
+    lib.pifcm_confusion.restype = st
     lib.pifcm_workspace_bytes.argtypes = [vp, P(i64), P(i64)]
     lib.pifcm_workspace_bytes.restype = st
     lib.pifcm_set_timing.argtypes = [vp, i32]
@@ -234,6 +243,32 @@ class Context:
             out["J_hist"] = hist[: out["iters"]].copy()
         return out
 
+    def ifcm_solve_slab(self, x, zbeg, zend, p: Params, lam, xi, centres, U_in, labels=False,
+                        want_hist=False):
+        """ifcm_solve on the planes [zbeg, zend) only, the rest of U_in held
+        fixed as context."""
+        import torch
+        vol = _volume(x)
+        c = np.ascontiguousarray(centres, np.float32)
+        _dev(U_in, torch.float32)
+        U_out = torch.empty((x.numel(), p.C), dtype=torch.float32, device=x.device)
+        lab = torch.empty(x.numel(), dtype=torch.uint8, device=x.device) if labels else None
+        cout = np.empty(p.C, np.float32)
+        J = np.zeros(1, np.float64)
+        it = np.zeros(1, np.int32)
+        hist = np.zeros(max(1, p.max_iter), np.float64)
+        self._check(self.lib.ifcm_solve_slab(
+            self.h, ct.byref(vol), int(zbeg), int(zend), ct.byref(p.c()), float(lam), float(xi),
+            _fp(c), U_in.data_ptr(), U_out.data_ptr(), _fp(cout),
+            None if lab is None else lab.data_ptr(), _dp(J), _ip(it),
+            _dp(hist) if want_hist else None))
+        out = dict(U=U_out, c=cout, J=float(J[0]), iters=int(it[0]))
+        if labels:
+            out["labels"] = lab
+        if want_hist:
+            out["J_hist"] = hist[: out["iters"]].copy()
+        return out
+
     def swarm_evaluate(self, xs, p: Params, particles, centres0, U0s, mode=PIFCM_SWARM_BATCHED):
         """xs: list of B (Z, Y, X) tensors; particles: (B, P, 2); centres0:
         (B, C); U0s: list of B (N_b, C) tensors."""
@@ -264,6 +299,20 @@ class Context:
                                            int(ckpt_every), _dp(J), _dp(dl), _dp(dx), _dp(dc)))
         return dict(J=float(J[0]), dlam=float(dl[0]), dxi=float(dx[0]), dc=dc)
 
+    def pifcm_confusion(self, labels, truth, C, K):
+        """Confusion counts (C, K) of device uint8 labels against device uint8
+        reference classes."""
+        import torch
+        lab = _dev(labels, torch.uint8)
+        tru = _dev(truth, torch.uint8)
+        if lab.numel() != tru.numel():
+            raise ValueError("labels and truth differ in size")
+        out = np.empty((C, K), np.int64)
+        self._check(self.lib.pifcm_confusion(self.h, lab.data_ptr(), tru.data_ptr(), lab.numel(),
+                                             int(C), int(K),
+                                             out.ctypes.data_as(ct.POINTER(ct.c_int64))))
+        return out
+
     def workspace_bytes(self):
         """Device bytes of workspace the context holds (its peak so far)."""
         d, h = ct.c_int64(), ct.c_int64()
@@ -282,8 +331,8 @@ class Context:
     def pifcm_tune(self, xs, p: Params, P):
         B = len(xs)
         vols = (_Volume * B)(*[_volume(x) for x in xs])
-        buf = ct.create_string_buffer(256)
-        self._check(self.lib.pifcm_tune(self.h, vols, B, ct.byref(p.c()), int(P), buf, 256))
+        buf = ct.create_string_buffer(1024)
+        self._check(self.lib.pifcm_tune(self.h, vols, B, ct.byref(p.c()), int(P), buf, 1024))
         return buf.value.decode()
 
     def pifcm_pso(self, xs, p: Params, streams, centres0, U0s, w=0.7, c1=1.5, c2=1.5,
@@ -311,3 +360,33 @@ class Context:
                                        _dp(r1), _dp(r2), float(w), float(c1), float(c2), _fp(c0),
                                        ptrs, int(mode), _dp(bp), _dp(bf), _dp(fh), _dp(ph)))
         return dict(best_pos=bp, best_fit=bf, fit_hist=fh, pos_hist=ph)
+
+    def pifcm_pso_interleaved(self, xs, p: Params, streams, centres0, U0s, steps=1, w=0.7, c1=1.5,
+                              c2=1.5, mode=PIFCM_SWARM_BATCHED):
+        """Swarm whose particles carry their own IFCM state, `steps`
+        iterations per generation.  Returns the outputs of pifcm_pso plus
+        U_best (list of B device (N_b, C) tensors) and centres_best (B, C)."""
+        import torch
+        B = len(xs)
+        vols = (_Volume * B)(*[_volume(x) for x in xs])
+        x0 = np.ascontiguousarray(streams["x0"], np.float64)
+        v0 = np.ascontiguousarray(streams["v0"], np.float64)
+        r1 = np.ascontiguousarray(streams["r1"], np.float64)
+        r2 = np.ascontiguousarray(streams["r2"], np.float64)
+        G, P = r1.shape[0], r1.shape[1]
+        if x0.shape != (P, 2) or v0.shape != (P, 2) or r2.shape != (G, P, 2):
+            raise ValueError("stream shapes do not agree")
+        c0 = np.ascontiguousarray(centres0, np.float32).reshape(B, p.C)
+        ptrs = (ct.c_void_p * B)(*[_dev(u).data_ptr() for u in U0s])
+        ub = [torch.empty((x.numel(), p.C), dtype=torch.float32, device=x.device) for x in xs]
+        uptr = (ct.c_void_p * B)(*[u.data_ptr() for u in ub])
+        cb = np.empty((B, p.C), np.float32)
+        bp = np.empty((B, 2))
+        bf = np.empty(B)
+        fh = np.empty((B, G, P))
+        ph = np.empty((B, G, P, 2))
+        self._check(self.lib.pifcm_pso_interleaved(
+            self.h, vols, B, ct.byref(p.c()), P, G, int(steps), _dp(x0), _dp(v0), _dp(r1), _dp(r2),
+            float(w), float(c1), float(c2), _fp(c0), ptrs, int(mode), _dp(bp), _dp(bf), _dp(fh),
+            _dp(ph), uptr, _fp(cb)))
+        return dict(best_pos=bp, best_fit=bf, fit_hist=fh, pos_hist=ph, U_best=ub, centres_best=cb)

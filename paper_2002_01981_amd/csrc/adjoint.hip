@@ -33,14 +33,34 @@ namespace pifcm {
 
 constexpr int kAdjThreads = 256;
 
-// Per-voxel stencil view: valid-neighbour loop over the 3x3x3 cube.
+// Per-voxel stencil view of the 3x3x3 cube: coordinates from the linear
+// index (32-bit: volumes hold fewer than 2^32 voxels) and, per axis, whether
+// the -1 and +1 neighbours exist.
 struct Nbr {
   int nx, ny, nz;
-  __device__ __forceinline__ void coords(size_t i, int& x, int& y, int& z) const {
-    x = (int)(i % nx);
-    const size_t r = i / nx;
-    y = (int)(r % ny);
-    z = (int)(r / ny);
+  int gx, gy, gz;
+  bool vxm, vxp, vym, vyp, vzm, vzp;
+  __device__ __forceinline__ Nbr(int nx_, int ny_, int nz_, size_t i) : nx(nx_), ny(ny_), nz(nz_) {
+    const uint32_t ii = (uint32_t)i;
+    gx = (int)(ii % (uint32_t)nx);
+    const uint32_t r = ii / (uint32_t)nx;
+    gy = (int)(r % (uint32_t)ny);
+    gz = (int)(r / (uint32_t)ny);
+    vxm = gx > 0;
+    vxp = gx < nx - 1;
+    vym = gy > 0;
+    vyp = gy < ny - 1;
+    vzm = gz > 0;
+    vzp = gz < nz - 1;
+  }
+  // Neighbour (dx, dy, dz) exists (offsets are compile-time constants).
+  __device__ __forceinline__ bool valid(int dx, int dy, int dz) const {
+    return (dx < 0 ? vxm : (dx > 0 ? vxp : true)) && (dy < 0 ? vym : (dy > 0 ? vyp : true)) &&
+           (dz < 0 ? vzm : (dz > 0 ? vzp : true));
+  }
+  // Linear index of neighbour (dx, dy, dz) of voxel i.
+  __device__ __forceinline__ size_t at(size_t i, int dx, int dy, int dz) const {
+    return (size_t)((long long)i + ((long long)dz * ny + dy) * nx + dx);
   }
 };
 
@@ -55,7 +75,6 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_point(const AdjArgs a) {
   __shared__ float s_red[(kAdjThreads / 64) * NV];
   const size_t N = (size_t)a.nx * a.ny * a.nz;
   const size_t i = (size_t)blockIdx.x * kAdjThreads + threadIdx.x;
-  const Nbr nb{a.nx, a.ny, a.nz};
   const float m = a.m;
   float acc[NV];
 #pragma unroll
@@ -74,8 +93,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_point(const AdjArgs a) {
     }
   }
   if (i < N) {
-    int gx, gy, gz;
-    nb.coords(i, gx, gy, gz);
+    const Nbr nb(a.nx, a.ny, a.nz, i);
     const float xv = a.x[i];
     const float ig = a.invg[i];
     const float gi = fabsf(ig);
@@ -84,13 +102,14 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_point(const AdjArgs a) {
 #pragma unroll
     for (int j = 0; j < C; ++j) Gn[j] = Fn[j] = 0.f;
     float qs = 0.f;
+#pragma unroll
     for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
       for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
-          const int X = gx + dx, Y = gy + dy, Z = gz + dz;
-          if ((dx | dy | dz) == 0 || X < 0 || X >= a.nx || Y < 0 || Y >= a.ny || Z < 0 || Z >= a.nz)
-            continue;
-          const size_t k = ((size_t)Z * a.ny + Y) * a.nx + X;
+          if ((dx | dy | dz) == 0 || !nb.valid(dx, dy, dz)) continue;
+          const size_t k = nb.at(i, dx, dy, dz);
           const float g = fabsf(xc - a.x[k]);
           const float q = qweight((dx != 0) + (dy != 0) + (dz != 0), a.q2_sqdist);
           qs += q;
@@ -191,9 +210,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_transpose(const AdjArgs a, 
   const size_t N = (size_t)a.nx * a.ny * a.nz;
   const size_t k = (size_t)blockIdx.x * kAdjThreads + threadIdx.x;
   if (k >= N) return;
-  const Nbr nb{a.nx, a.ny, a.nz};
-  int gx, gy, gz;
-  nb.coords(k, gx, gy, gz);
+  const Nbr nb(a.nx, a.ny, a.nz, k);
   const float xk = a.x[k];
   float u[C], out[C];
   load_row<C>(as_global(a.U) + k * C, u);
@@ -202,13 +219,14 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_transpose(const AdjArgs a, 
 #pragma unroll
     for (int j = 0; j < C; ++j) out[j] = 0.f;
   }
+#pragma unroll
   for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
     for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
-        const int X = gx + dx, Y = gy + dy, Z = gz + dz;
-        if ((dx | dy | dz) == 0 || X < 0 || X >= a.nx || Y < 0 || Y >= a.ny || Z < 0 || Z >= a.nz)
-          continue;
-        const size_t i = ((size_t)Z * a.ny + Y) * a.nx + X;
+        if ((dx | dy | dz) == 0 || !nb.valid(dx, dy, dz)) continue;
+        const size_t i = nb.at(k, dx, dy, dz);
         const float igi = a.invg[i];
         const float xci = igi < 0.f ? a.x[i] - 1.f : a.x[i];
         const float g = fabsf(xci - xk);  // g_ik as voxel i uses it

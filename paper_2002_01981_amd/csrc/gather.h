@@ -120,7 +120,7 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
     const int tyi = rest % vd.nty;
     const int tzi = rest / vd.nty;
     const int x0 = txi * kWX, y0 = tyi * kWY;
-    const int zlo = tzi * vd.zc, zhi = min(zlo + vd.zc, nz);
+    const int zlo = vd.zbeg + tzi * vd.zc, zhi = min(zlo + vd.zc, vd.zend);
     const int gx = x0 + tx, gy = y0 + ty;
     const bool active = gx < nx && gy < ny;
     const int hx = x0 - 1 + hcx, hy = y0 - 1 + hcy;

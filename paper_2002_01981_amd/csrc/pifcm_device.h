@@ -42,7 +42,8 @@ struct VolDev {
   int32_t zc;          // planes per tile
   int32_t ntx, nty, ntz;
   int32_t tiles;       // ntx * nty * ntz (gather kernels)
-  int32_t tiles1d;     // ceil(N / voxels per block) (pointwise kernels)
+  int32_t tiles1d;     // ceil(active voxels / voxels per block) (pointwise kernels)
+  int32_t zbeg, zend;  // planes iterated; the others are fixed context
   int32_t pad;
 };
 

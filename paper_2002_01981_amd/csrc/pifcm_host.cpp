@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <string>
 #include <tuple>
@@ -56,6 +57,8 @@ struct pifcm_ctx {
   DevBuf adj_ck, adj_seg, adj_bar, adj_pq, adj_misc;  // ifcm_backward workspace
   DevBuf tune_u0, tune_state;                          // pifcm_tune workspace
   DevBuf ring_tab;                                     // general-neighbourhood offsets
+  DevBuf conf;                                         // pifcm_confusion counts
+  DevBuf pso_state;                                    // pifcm_pso_interleaved states
   int ring_n = 0;                                      // offsets in ring_tab
   int ring_gen = 0;                                    // rebuilds of ring_tab
   int ring_key[3] = {0, -1, 0};                        // (V, flags, bits of h) of ring_tab
@@ -212,20 +215,26 @@ TileShape shape_for(pifcm_ctx* ctx, int C, bool m2, const pifcm_volume& v) {
   return t;
 }
 
-VolDev make_vol(const pifcm_volume& v, const float* invg, TileShape ts) {
+// Launch descriptor of a volume whose planes [zbeg, zend) are iterated
+// (zend < 0: all planes).
+VolDev make_vol(const pifcm_volume& v, const float* invg, TileShape ts, int zbeg = 0, int zend = -1) {
+  if (zend < 0) zend = v.nz;
   VolDev d{};
   d.x = v.x;
   d.invg = invg;
   d.nx = v.nx;
   d.ny = v.ny;
   d.nz = v.nz;
-  d.zc = std::max(1, std::min(ts.zc, v.nz));
+  d.zbeg = zbeg;
+  d.zend = zend;
+  const int nact = zend - zbeg;
+  d.zc = std::max(1, std::min(ts.zc, nact));
   d.ntx = (v.nx + kWaveTileX - 1) / kWaveTileX;
   d.nty = (v.ny + kWaveTileY - 1) / kWaveTileY;
-  d.ntz = (v.nz + d.zc - 1) / d.zc;
+  d.ntz = (nact + d.zc - 1) / d.zc;
   d.tiles = d.ntx * d.nty * d.ntz;
   const size_t per = (size_t)256 * kFcmVoxPerThread;
-  d.tiles1d = (int)((nvox(v) + per - 1) / per);
+  d.tiles1d = (int)(((size_t)v.nx * v.ny * nact + per - 1) / per);
   return d;
 }
 
@@ -445,7 +454,7 @@ void pifcm_destroy(pifcm_ctx* ctx) {
   if (ctx->graph.graph) (void)hipGraphDestroy(ctx->graph.graph);
   for (DevBuf* b : {&ctx->invg, &ctx->ubuf, &ctx->partials, &ctx->states, &ctx->jhist, &ctx->tvol,
                     &ctx->tpair, &ctx->flags, &ctx->adj_ck, &ctx->adj_seg, &ctx->adj_bar,
-                    &ctx->adj_pq, &ctx->adj_misc, &ctx->tune_u0, &ctx->tune_state, &ctx->ring_tab})
+                    &ctx->adj_pq, &ctx->adj_misc, &ctx->tune_u0, &ctx->tune_state, &ctx->ring_tab, &ctx->conf, &ctx->pso_state})
     if (b->p) (void)hipFree(b->p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
@@ -492,10 +501,33 @@ pifcm_status pifcm_workspace_bytes(pifcm_ctx* ctx, int64_t* device_bytes, int64_
   for (const DevBuf* b : {&ctx->invg, &ctx->ubuf, &ctx->partials, &ctx->states, &ctx->jhist,
                           &ctx->tvol, &ctx->tpair, &ctx->flags, &ctx->adj_ck, &ctx->adj_seg,
                           &ctx->adj_bar, &ctx->adj_pq, &ctx->adj_misc, &ctx->tune_u0,
-                          &ctx->tune_state, &ctx->ring_tab})
+                          &ctx->tune_state, &ctx->ring_tab, &ctx->conf, &ctx->pso_state})
     d += (int64_t)b->cap;
   if (device_bytes) *device_bytes = d;
   if (pinned_bytes) *pinned_bytes = (int64_t)ctx->pinned_cap;
+  return PIFCM_OK;
+}
+
+pifcm_status pifcm_confusion(pifcm_ctx* ctx, const uint8_t* labels, const uint8_t* truth, int64_t n,
+                             int32_t C, int32_t K, int64_t* counts_out) {
+  if (!ctx) return PIFCM_E_INVALID;
+  ctx->err.clear();
+  if (!labels || !truth || !counts_out) return fail(ctx, PIFCM_E_INVALID, "labels, truth and counts_out must be non-NULL");
+  if (n < 1) return fail(ctx, PIFCM_E_INVALID, "n = %lld must be >= 1", (long long)n);
+  if (C < 1 || C > kMaxC || K < 1 || K > kMaxC)
+    return fail(ctx, PIFCM_E_INVALID, "C = %d, K = %d outside [1, %d]", C, K, kMaxC);
+  const size_t nb = (size_t)C * K + 1;
+  TRY(begin(ctx));
+  TRY(ensure(ctx, ctx->conf, nb * sizeof(unsigned long long), "confusion counts"));
+  TRY(ensure_pinned(ctx, nb * sizeof(unsigned long long)));
+  HIPCHK(hipMemsetAsync(ctx->conf.p, 0, nb * sizeof(unsigned long long), ctx->s));
+  HIPCHK(launch_confusion(labels, truth, (size_t)n, C, K, (unsigned long long*)ctx->conf.p, ctx->s));
+  HIPCHK(hipMemcpyAsync(ctx->pinned, ctx->conf.p, nb * sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->s));
+  HIPCHK(hipStreamSynchronize(ctx->s));
+  TRY(finish(ctx));
+  const unsigned long long* h = (const unsigned long long*)ctx->pinned;
+  if (h[nb - 1]) return fail(ctx, PIFCM_E_INVALID, "%llu labels or classes out of range", h[nb - 1]);
+  for (size_t t = 0; t + 1 < nb; ++t) counts_out[t] = (int64_t)h[t];
   return PIFCM_OK;
 }
 
@@ -533,7 +565,9 @@ namespace {
 pifcm_status solve_impl(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
                         float lambda, float xi, const float* centres_in, const float* U_in,
                         float* U_out, float* centres_out, uint8_t* labels_out, double* J_out,
-                        int32_t* iters_out, double* J_hist_out) {
+                        int32_t* iters_out, double* J_hist_out, int zbeg = 0, int zend = -1) {
+  if (zend < 0) zend = vol->nz;
+  const bool slab = zbeg > 0 || zend < vol->nz;
   const int C = p->C;
   const bool m2 = p->m == 2.0f;
   const int kind = kind_of(p, lambda == 0.0f && xi == 0.0f);
@@ -543,7 +577,7 @@ pifcm_status solve_impl(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_par
   const float* u0s[1] = {U_in};
   TRY(prepare_volumes(ctx, vol, 1, C, u0s, off));
   const TileShape ts = shape_for(ctx, C, m2, *vol);
-  std::vector<VolDev> vh{make_vol(*vol, (const float*)ctx->invg.p, ts)};
+  std::vector<VolDev> vh{make_vol(*vol, (const float*)ctx->invg.p, ts, zbeg, zend)};
   const int slots = std::max(vh[0].tiles, vh[0].tiles1d);
   TRY(ensure(ctx, ctx->ubuf, N * C * sizeof(float), "memberships"));
   TRY(ensure(ctx, ctx->partials, (size_t)slots * (2 * C + 1) * sizeof(float), "tile sums"));
@@ -570,6 +604,11 @@ pifcm_status solve_impl(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_par
   HIPCHK(hipMemcpyAsync(ctx->tvol.p, pin + sizeof(SolveState) + sizeof(PairDev), sizeof(VolDev),
                         hipMemcpyHostToDevice, ctx->s));
   if (!U_in) HIPCHK(launch_init_u(C, vol->x, N, st_dev, p->m, m2, ubuf, ctx->s));
+  if (slab) {
+    // Planes outside the slab keep U_in in both iteration buffers.
+    HIPCHK(hipMemcpyAsync(U_out, U_in, N * C * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+    HIPCHK(hipMemcpyAsync(ubuf, U_in, N * C * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+  }
 
   LaunchArgs a = make_args(ctx, (const VolDev*)ctx->tvol.p, (const PairDev*)ctx->tpair.p, vh, 1, 1, kind, p);
   const int occ = occupancy_of(kind, C, ts.nw, m2, true);
@@ -657,6 +696,32 @@ pifcm_status ifcm_solve(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_par
   return PIFCM_OK;
 }
 
+pifcm_status ifcm_solve_slab(pifcm_ctx* ctx, const pifcm_volume* vol, int32_t zbeg, int32_t zend,
+                             const pifcm_params* p, float lambda, float xi, const float* centres_in,
+                             const float* U_in, float* U_out, float* centres_out,
+                             uint8_t* labels_out, double* J_out, int32_t* iters_out,
+                             double* J_hist_out) {
+  if (!ctx) return PIFCM_E_INVALID;
+  ctx->err.clear();
+  TRY(check_solve_args(ctx, vol, p, lambda, xi, centres_in, U_in, U_out));
+  if (!U_in) return fail(ctx, PIFCM_E_INVALID, "slab mode needs U_in (the context memberships)");
+  if (zbeg < 0 || zend > vol->nz || zbeg >= zend)
+    return fail(ctx, PIFCM_E_INVALID, "planes [%d, %d) outside [0, %d)", zbeg, zend, vol->nz);
+  TRY(begin(ctx));
+  float c_tmp[kMaxC];
+  double J = 0.0;
+  int32_t T = 0;
+  std::vector<double> jh((size_t)std::max(1, p->max_iter));
+  TRY(solve_impl(ctx, vol, p, lambda, xi, centres_in, U_in, U_out, c_tmp, labels_out, &J, &T,
+                 J_hist_out ? jh.data() : nullptr, zbeg, zend));
+  TRY(finish(ctx));
+  if (centres_out) std::memcpy(centres_out, c_tmp, sizeof(float) * p->C);
+  if (J_out) *J_out = J;
+  if (iters_out) *iters_out = T;
+  if (J_hist_out) std::memcpy(J_hist_out, jh.data(), sizeof(double) * (size_t)T);
+  return PIFCM_OK;
+}
+
 pifcm_status pifcm_fcm_init(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
                             float* U0_out, float* centres_out, int32_t* iters_out) {
   if (!ctx) return PIFCM_E_INVALID;
@@ -682,35 +747,24 @@ pifcm_status pifcm_fcm_init(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm
   return PIFCM_OK;
 }
 
-pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
-                            const pifcm_params* p, const float* particles, int32_t P,
-                            const float* centres0, const float* const* U0, double* fitness_out,
-                            float* centres_out, int32_t* iters_out, int32_t mode) {
-  if (!ctx) return PIFCM_E_INVALID;
-  ctx->err.clear();
-  if (!vols || B < 1 || B > kMaxBatchVols)
-    return fail(ctx, PIFCM_E_INVALID, "B = %d outside [1, %d]", B, kMaxBatchVols);
-  if (P < 1 || (long)B * P > kMaxPairs)
-    return fail(ctx, PIFCM_E_INVALID, "P = %d: need 1 <= P and B * P <= %d", P, kMaxPairs);
-  if (mode != PIFCM_SWARM_BATCHED && mode != PIFCM_SWARM_PLAIN)
-    return fail(ctx, PIFCM_E_INVALID, "unknown mode %d", mode);
-  TRY(check_params(ctx, p));
-  if (!particles || !centres0 || !U0 || !fitness_out)
-    return fail(ctx, PIFCM_E_INVALID, "particles, centres0, U0 and fitness_out must be non-NULL");
+}  // extern "C"
+
+namespace {
+
+// The swarm evaluation proper: B volumes x P particles, pair k = b * P + q
+// starting from (centres_pp[k], U0_pp[k]); U0_check (per volume, may be
+// NULL) are validated as memberships.  If state_out is given, the final
+// memberships of pair k are copied to state_out[k] (device [N_b][C]).
+pifcm_status swarm_core(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, const pifcm_params* p,
+                        const float* particles, int32_t P, const float* centres_pp,
+                        const float* const* U0_pp, const float* const* U0_check,
+                        float* const* state_out, double* fitness_out, float* centres_out,
+                        int32_t* iters_out, int32_t mode) {
   const int C = p->C;
   const bool m2 = p->m == 2.0f;
-  for (int b = 0; b < B; ++b) {
-    TRY(check_volume(ctx, &vols[b]));
-    if (!U0[b] || !aligned16(U0[b])) return fail(ctx, PIFCM_E_INVALID, "U0[%d] is NULL or not 16-byte aligned", b);
-    for (int j = 0; j < C; ++j)
-      if (!std::isfinite(centres0[b * C + j])) return fail(ctx, PIFCM_E_INVALID, "centres0[%d][%d] is not finite", b, j);
-  }
-  for (long k = 0; k < 2L * B * P; ++k)
-    if (!(std::fabs(particles[k]) <= kMaxWeight))
-      return fail(ctx, PIFCM_E_INVALID, "particle value %ld is not finite or exceeds %g", k, kMaxWeight);
   TRY(begin(ctx));
   std::vector<size_t> off;
-  TRY(prepare_volumes(ctx, vols, B, C, U0, off));
+  TRY(prepare_volumes(ctx, vols, B, C, U0_check, off));
 
   // Tile shape: one per launch (the batched kernel has one TY).
   const TileShape ts0 = shape_for(ctx, C, m2, vols[0]);
@@ -746,9 +800,9 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
     const int tb = std::max(vh[b].tiles, vh[b].tiles1d);
     for (int q = 0; q < P; ++q) {
       const size_t k = (size_t)b * P + q;
-      hs[k] = init_state(centres0 + (size_t)b * C, C, particles[2 * k], particles[2 * k + 1], p, nullptr);
+      hs[k] = init_state(centres_pp + k * C, C, particles[2 * k], particles[2 * k + 1], p, nullptr);
       PairDev& pr = hp[k];
-      pr.U0 = U0[b];
+      pr.U0 = U0_pp[k];
       pr.Ua = (float*)((char*)ctx->ubuf.p + uoff[b]) + (size_t)q * 2 * ustride;
       pr.Ub = pr.Ua + ustride;
       pr.st = st_dev + k;
@@ -857,6 +911,17 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
   HIPCHK(hipMemcpyAsync(hs, st_dev, npairs * sizeof(SolveState), hipMemcpyDeviceToHost, ctx->s));
   HIPCHK(hipStreamSynchronize(ctx->s));
   TRY(timing_collect(ctx, launches));
+  if (state_out) {
+    for (int b = 0; b < B; ++b)
+      for (int q = 0; q < P; ++q) {
+        const size_t k = (size_t)b * P + q;
+        const float* fin = u_state_of(hp[k], hs[k].iter);
+        if (fin != state_out[k])
+          HIPCHK(hipMemcpyAsync(state_out[k], fin, nvox(vols[b]) * C * sizeof(float), hipMemcpyDeviceToDevice,
+                                ctx->s));
+      }
+    HIPCHK(hipStreamSynchronize(ctx->s));
+  }
   TRY(finish(ctx));
   for (size_t k = 0; k < npairs; ++k) {
     const int T = hs[k].iter;
@@ -866,6 +931,46 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
     if (iters_out) iters_out[k] = T;
   }
   return PIFCM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
+                            const pifcm_params* p, const float* particles, int32_t P,
+                            const float* centres0, const float* const* U0, double* fitness_out,
+                            float* centres_out, int32_t* iters_out, int32_t mode) {
+  if (!ctx) return PIFCM_E_INVALID;
+  ctx->err.clear();
+  if (!vols || B < 1 || B > kMaxBatchVols)
+    return fail(ctx, PIFCM_E_INVALID, "B = %d outside [1, %d]", B, kMaxBatchVols);
+  if (P < 1 || (long)B * P > kMaxPairs)
+    return fail(ctx, PIFCM_E_INVALID, "P = %d: need 1 <= P and B * P <= %d", P, kMaxPairs);
+  if (mode != PIFCM_SWARM_BATCHED && mode != PIFCM_SWARM_PLAIN)
+    return fail(ctx, PIFCM_E_INVALID, "unknown mode %d", mode);
+  TRY(check_params(ctx, p));
+  if (!particles || !centres0 || !U0 || !fitness_out)
+    return fail(ctx, PIFCM_E_INVALID, "particles, centres0, U0 and fitness_out must be non-NULL");
+  const int C = p->C;
+  for (int b = 0; b < B; ++b) {
+    TRY(check_volume(ctx, &vols[b]));
+    if (!U0[b] || !aligned16(U0[b])) return fail(ctx, PIFCM_E_INVALID, "U0[%d] is NULL or not 16-byte aligned", b);
+    for (int j = 0; j < C; ++j)
+      if (!std::isfinite(centres0[b * C + j])) return fail(ctx, PIFCM_E_INVALID, "centres0[%d][%d] is not finite", b, j);
+  }
+  for (long k = 0; k < 2L * B * P; ++k)
+    if (!(std::fabs(particles[k]) <= kMaxWeight))
+      return fail(ctx, PIFCM_E_INVALID, "particle value %ld is not finite or exceeds %g", k, kMaxWeight);
+  std::vector<float> cpp((size_t)B * P * C);
+  std::vector<const float*> upp((size_t)B * P);
+  for (int b = 0; b < B; ++b)
+    for (int q = 0; q < P; ++q) {
+      upp[(size_t)b * P + q] = U0[b];
+      for (int j = 0; j < C; ++j) cpp[((size_t)b * P + q) * C + j] = centres0[b * C + j];
+    }
+  return swarm_core(ctx, vols, B, p, particles, P, cpp.data(), upp.data(), U0, nullptr, fitness_out,
+                    centres_out, iters_out, mode);
 }
 
 pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
@@ -1116,11 +1221,11 @@ pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
   std::vector<Cand> cands;
   cands.push_back({4, 32});  // the default decomposition: the reference
   const int nws[3] = {1, 2, 4};
-  const int zcs[4] = {8, 16, 32, 64};
+  const int zcs[5] = {8, 16, 32, 64, 128};
   for (int nw : nws) {
     if (C != 4 && nw != 4) continue;
     for (int zc : zcs) {
-      if (zc > maxz && zc != 8) continue;
+      if (zc / 2 >= maxz && zc != 8) continue;  // one candidate covers the whole column
       if (nw == 4 && zc == 32) continue;
       cands.push_back({nw, zc});
     }
@@ -1131,7 +1236,8 @@ pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
   std::vector<float> cen_ref((size_t)B * P * C), cen((size_t)B * P * C);
   double best_ms = 1e300;
   Cand best = cands[0];
-  char desc[256] = {0};
+  char desc[1024] = {0};
+  std::string tried;
   for (size_t ci = 0; ci < cands.size(); ++ci) {
     for (int b = 0; b < B; ++b) {
       TileShape t;
@@ -1162,6 +1268,10 @@ pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
           for (size_t k = 0; k < cen.size(); ++k)
             ok = ok && std::fabs(cen[k] - cen_ref[k]) <= 1e-5f * std::max(1e-3f, std::fabs(cen_ref[k]));
         }
+        char one[48];
+        snprintf(one, sizeof one, "%s%dx%d:%.3f%s", tried.empty() ? "" : " ", cands[ci].nw, cands[ci].zc, ms,
+                 ok ? "" : "(differs)");
+        tried += one;
         if (ok && ms < best_ms) {
           best_ms = ms;
           best = cands[ci];
@@ -1182,8 +1292,8 @@ pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
     t.zc = best.zc;
     ctx->tuned[std::make_tuple(C, (int)m2, vols[b].nx, vols[b].ny, vols[b].nz)] = t;
   }
-  snprintf(desc, sizeof desc, "waves_per_group=%d planes_per_tile=%d step_ms=%.4f candidates=%zu",
-           best.nw, best.zc, best_ms, cands.size());
+  snprintf(desc, sizeof desc, "waves_per_group=%d planes_per_tile=%d step_ms=%.4f candidates=%zu [%s]",
+           best.nw, best.zc, best_ms, cands.size(), tried.c_str());
   if (best_out && best_len > 0) {
     std::strncpy(best_out, desc, (size_t)best_len - 1);
     best_out[best_len - 1] = 0;
@@ -1192,22 +1302,27 @@ pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
   return PIFCM_OK;
 }
 
-pifcm_status pifcm_pso(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, const pifcm_params* p,
-                       int32_t P, int32_t G, const double* x0, const double* v0, const double* r1,
-                       const double* r2, double w, double c1, double c2, const float* centres0,
-                       const float* const* U0, int32_t mode, double* best_pos, double* best_fit,
-                       double* fit_hist, double* pos_hist) {
-  if (!ctx) return PIFCM_E_INVALID;
-  ctx->err.clear();
+}  // extern "C"
+
+namespace {
+
+// Synchronous global-best swarm bookkeeping (Algorithm 1, steps 5-8) around
+// an evaluation callback eval(g, particles [B][P][2] as float, fitness).
+// best_k (may be NULL) receives, per volume, the particle holding the best.
+pifcm_status pso_run(pifcm_ctx* ctx, int32_t B, int32_t P, int32_t G, const double* x0,
+                     const double* v0, const double* r1, const double* r2, double w, double c1,
+                     double c2, const std::function<pifcm_status(int, const float*, double*)>& eval,
+                     double* best_pos, double* best_fit, double* fit_hist, double* pos_hist,
+                     int* best_k) {
   if (B < 1 || B > kMaxBatchVols || P < 1 || G < 1 || (long)B * P > kMaxPairs)
     return fail(ctx, PIFCM_E_INVALID, "B = %d, P = %d, G = %d out of range", B, P, G);
   if (!x0 || !v0 || !r1 || !r2 || !best_pos || !best_fit)
     return fail(ctx, PIFCM_E_INVALID, "x0, v0, r1, r2, best_pos and best_fit must be non-NULL");
   if (!std::isfinite(w) || !std::isfinite(c1) || !std::isfinite(c2))
     return fail(ctx, PIFCM_E_INVALID, "w, c1, c2 must be finite");
-  const int C = p ? p->C : 0;
   std::vector<double> pos((size_t)B * P * 2), vel((size_t)B * P * 2), pb((size_t)B * P * 2);
   std::vector<double> pbf((size_t)B * P), gb((size_t)B * 2), gbf(B);
+  std::vector<int> gk(B, 0);
   std::vector<float> parts((size_t)B * P * 2);
   std::vector<double> fit((size_t)B * P);
   for (int b = 0; b < B; ++b)
@@ -1217,8 +1332,7 @@ pifcm_status pifcm_pso(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, cons
     }
   for (int g = 0; g < G; ++g) {
     for (size_t k = 0; k < parts.size(); ++k) parts[k] = (float)pos[k];
-    TRY(swarm_evaluate(ctx, vols, B, p, parts.data(), P, centres0, U0, fit.data(), nullptr, nullptr,
-                       mode));
+    TRY(eval(g, parts.data(), fit.data()));
     for (int b = 0; b < B; ++b) {
       for (int q = 0; q < P; ++q) {
         const size_t k = (size_t)b * P + q;
@@ -1240,6 +1354,7 @@ pifcm_status pifcm_pso(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, cons
           gbf[b] = pbf[k];
           gb[b * 2] = pb[k * 2];
           gb[b * 2 + 1] = pb[k * 2 + 1];
+          gk[b] = q;
           have = true;
         }
       }
@@ -1260,8 +1375,97 @@ pifcm_status pifcm_pso(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, cons
     best_pos[b * 2] = gb[b * 2];
     best_pos[b * 2 + 1] = gb[b * 2 + 1];
     best_fit[b] = gbf[b];
+    if (best_k) best_k[b] = gk[b];
   }
-  (void)C;
+  return PIFCM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pifcm_status pifcm_pso(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, const pifcm_params* p,
+                       int32_t P, int32_t G, const double* x0, const double* v0, const double* r1,
+                       const double* r2, double w, double c1, double c2, const float* centres0,
+                       const float* const* U0, int32_t mode, double* best_pos, double* best_fit,
+                       double* fit_hist, double* pos_hist) {
+  if (!ctx) return PIFCM_E_INVALID;
+  ctx->err.clear();
+  auto eval = [&](int, const float* parts, double* fit) -> pifcm_status {
+    return swarm_evaluate(ctx, vols, B, p, parts, P, centres0, U0, fit, nullptr, nullptr, mode);
+  };
+  return pso_run(ctx, B, P, G, x0, v0, r1, r2, w, c1, c2, eval, best_pos, best_fit, fit_hist,
+                 pos_hist, nullptr);
+}
+
+pifcm_status pifcm_pso_interleaved(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
+                                   const pifcm_params* p, int32_t P, int32_t G, int32_t steps,
+                                   const double* x0, const double* v0, const double* r1,
+                                   const double* r2, double w, double c1, double c2,
+                                   const float* centres0, const float* const* U0, int32_t mode,
+                                   double* best_pos, double* best_fit, double* fit_hist,
+                                   double* pos_hist, float* const* U_best_out,
+                                   float* centres_best_out) {
+  if (!ctx) return PIFCM_E_INVALID;
+  ctx->err.clear();
+  if (steps < 1 || steps > 1000000) return fail(ctx, PIFCM_E_INVALID, "steps = %d must be in [1, 1e6]", steps);
+  if (!vols || B < 1 || B > kMaxBatchVols || P < 1 || (long)B * P > kMaxPairs)
+    return fail(ctx, PIFCM_E_INVALID, "B = %d, P = %d out of range", B, P);
+  TRY(check_params(ctx, p));
+  if (!centres0 || !U0) return fail(ctx, PIFCM_E_INVALID, "centres0 and U0 must be non-NULL");
+  const int C = p->C;
+  for (int b = 0; b < B; ++b) {
+    TRY(check_volume(ctx, &vols[b]));
+    if (!U0[b] || !aligned16(U0[b])) return fail(ctx, PIFCM_E_INVALID, "U0[%d] is NULL or not 16-byte aligned", b);
+    if (U_best_out && (!U_best_out[b] || !aligned16(U_best_out[b])))
+      return fail(ctx, PIFCM_E_INVALID, "U_best_out[%d] is NULL or not 16-byte aligned", b);
+  }
+  // Per-particle states, one membership buffer per (volume, particle).
+  std::vector<size_t> soff((size_t)B * P);
+  size_t total = 0;
+  for (int b = 0; b < B; ++b)
+    for (int q = 0; q < P; ++q) {
+      soff[(size_t)b * P + q] = total;
+      total += (nvox(vols[b]) * C + 63) / 64 * 64;
+    }
+  TRY(begin(ctx));
+  TRY(ensure(ctx, ctx->pso_state, total * sizeof(float), "particle states"));
+  std::vector<float*> st((size_t)B * P);
+  std::vector<float> cen((size_t)B * P * C), cnext((size_t)B * P * C);
+  for (int b = 0; b < B; ++b)
+    for (int q = 0; q < P; ++q) {
+      const size_t k = (size_t)b * P + q;
+      st[k] = (float*)ctx->pso_state.p + soff[k];
+      HIPCHK(hipMemcpyAsync(st[k], U0[b], nvox(vols[b]) * C * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+      for (int j = 0; j < C; ++j) cen[k * C + j] = centres0[b * C + j];
+    }
+  HIPCHK(hipStreamSynchronize(ctx->s));
+  pifcm_params ps = *p;
+  ps.max_iter = steps;
+  ps.eps = 0.f;
+  std::vector<const float*> stc(st.begin(), st.end());
+  auto eval = [&](int g, const float* parts, double* fit) -> pifcm_status {
+    for (long k = 0; k < 2L * B * P; ++k)
+      if (!(std::fabs(parts[k]) <= kMaxWeight))
+        return fail(ctx, PIFCM_E_INVALID, "particle value %ld is not finite or exceeds %g", k, kMaxWeight);
+    TRY(swarm_core(ctx, vols, B, &ps, parts, P, cen.data(), stc.data(), g == 0 ? U0 : nullptr,
+                   st.data(), fit, cnext.data(), nullptr, mode));
+    cen.swap(cnext);
+    return PIFCM_OK;
+  };
+  std::vector<int> bk(B);
+  TRY(pso_run(ctx, B, P, G, x0, v0, r1, r2, w, c1, c2, eval, best_pos, best_fit, fit_hist, pos_hist,
+              bk.data()));
+  for (int b = 0; b < B; ++b) {
+    const size_t k = (size_t)b * P + bk[b];
+    if (U_best_out)
+      HIPCHK(hipMemcpyAsync(U_best_out[b], st[k], nvox(vols[b]) * C * sizeof(float), hipMemcpyDeviceToDevice,
+                            ctx->s));
+    if (centres_best_out)
+      for (int j = 0; j < C; ++j) centres_best_out[b * C + j] = cen[k * C + j];
+  }
+  HIPCHK(hipStreamSynchronize(ctx->s));
+  TRY(finish(ctx));
   return PIFCM_OK;
 }
 

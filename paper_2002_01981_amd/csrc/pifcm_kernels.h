@@ -25,6 +25,10 @@ hipError_t launch_invariants(const float* x, float* invg, int nx, int ny, int nz
                              hipStream_t s);
 hipError_t launch_check_rows(const float* U, size_t N, int C, int* flag, hipStream_t s);
 hipError_t launch_labels(const float* U, size_t N, int C, uint8_t* out, hipStream_t s);
+// counts (device, C * K + 1 entries, zeroed by the caller) += confusion of
+// labels against truth; the last entry counts out-of-range pairs.
+hipError_t launch_confusion(const uint8_t* labels, const uint8_t* truth, size_t N, int C, int K,
+                            unsigned long long* counts, hipStream_t s);
 hipError_t launch_permute(const float* U, size_t N, int C, const int32_t* perm, float* out,
                           hipStream_t s);
 // Min-max normalisation: exact min/max keys into mm[0..1] (mm preset to

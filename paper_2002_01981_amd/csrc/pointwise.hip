@@ -33,11 +33,12 @@ __global__ __launch_bounds__(256) void k_fcm_point(const LaunchArgs a) {
     float cj[C];
 #pragma unroll
     for (int j = 0; j < C; ++j) cj[j] = ld_const(&st->c[(STEP ? t - 1 : t) & 1][j]);
-    const size_t N = (size_t)vd.nx * vd.ny * vd.nz;
+    const size_t psz = (size_t)vd.nx * vd.ny;
+    const size_t N = (size_t)vd.zend * psz;  // end of the planes iterated
     float acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.f;
-    const size_t base = (size_t)tile * NT * kFcmVoxPerThread;
+    const size_t base = (size_t)vd.zbeg * psz + (size_t)tile * NT * kFcmVoxPerThread;
 #pragma unroll 2
     for (int k = 0; k < kFcmVoxPerThread; ++k) {
       const size_t i = base + (size_t)k * NT + threadIdx.x;
@@ -157,6 +158,27 @@ __global__ __launch_bounds__(256) void k_labels(const float* __restrict__ U, siz
     }
     out[i] = (uint8_t)best;
   }
+}
+
+// Confusion counts of labels (0..C-1) against reference classes (0..K-1):
+// counts[j * K + k] += #{i : labels_i = j, truth_i = k}; pairs outside the
+// ranges go to counts[C * K].  Per-block LDS histogram, then one atomic add
+// per bin (integer sums: the result does not depend on the order).
+__global__ __launch_bounds__(256) void k_confusion(const uint8_t* __restrict__ labels,
+                                                   const uint8_t* __restrict__ truth, size_t N,
+                                                   int C, int K, unsigned long long* counts) {
+  __shared__ uint32_t h[kMaxC * kMaxC + 1];
+  const int nb = C * K + 1;
+  for (int t = threadIdx.x; t < nb; t += blockDim.x) h[t] = 0u;
+  __syncthreads();
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int j = labels[i], k = truth[i];
+    atomicAdd(&h[(j < C && k < K) ? j * K + k : C * K], 1u);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nb; t += blockDim.x)
+    if (h[t]) atomicAdd(&counts[t], (unsigned long long)h[t]);
 }
 
 struct Perm {
@@ -321,6 +343,12 @@ hipError_t launch_check_rows(const float* U, size_t N, int C, int* flag, hipStre
 
 hipError_t launch_labels(const float* U, size_t N, int C, uint8_t* out, hipStream_t s) {
   hipLaunchKernelGGL(k_labels, dim3(small_grid(N)), dim3(256), 0, s, U, N, C, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_confusion(const uint8_t* labels, const uint8_t* truth, size_t N, int C, int K,
+                            unsigned long long* counts, hipStream_t s) {
+  hipLaunchKernelGGL(k_confusion, dim3(small_grid(N)), dim3(256), 0, s, labels, truth, N, C, K, counts);
   return hipGetLastError();
 }
 

@@ -39,11 +39,12 @@ __global__ __launch_bounds__(256) void k_ifcm_ring(const LaunchArgs a) {
     for (int j = 0; j < C; ++j) cj[j] = ld_const(&st->c[(STEP ? t - 1 : t) & 1][j]);
     const float lam = ld_const(&st->lam), xi = ld_const(&st->xi);
     const int nx = vd.nx, ny = vd.ny, nz = vd.nz;
-    const size_t N = (size_t)nx * ny * nz;
+    const size_t psz = (size_t)nx * ny;
+    const size_t N = (size_t)vd.zend * psz;  // end of the planes iterated
     float acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.f;
-    const size_t base = (size_t)tile * NT * kFcmVoxPerThread;
+    const size_t base = (size_t)vd.zbeg * psz + (size_t)tile * NT * kFcmVoxPerThread;
     for (int k = 0; k < kFcmVoxPerThread; ++k) {
       const size_t i = base + (size_t)k * NT + threadIdx.x;
       if (i >= N) break;

@@ -373,3 +373,96 @@ def test_thread_count_does_not_change_results(orc):
     assert np.array_equal(a["U"], b["U"]) and np.array_equal(a["c"], b["c"])
     assert a["J"] == b["J"]
     assert math.isfinite(a["J"])
+
+
+def test_pso_interleaved_frozen_swarm_is_one_long_solve(orc):
+    """With a frozen swarm each particle keeps its (lambda, xi), so after
+    generation g its state is (g + 1) * steps iterations of one solve from
+    (c0, U0): the carried state must reproduce a long solve exactly."""
+    x, p, c0, U0, st = _pso_case(orc, P=3, G=4, seed=9)
+    st = dict(x0=st["x0"], v0=np.zeros_like(st["v0"]), r1=np.zeros_like(st["r1"]),
+              r2=np.zeros_like(st["r2"]))
+    steps = 2
+    out = orc.pso_interleaved(x, c0, U0, p, st, steps=steps)
+    for g in range(4):
+        np.testing.assert_array_equal(out["pos_hist"][g], st["x0"])
+        for k in range(3):
+            lam, xi = st["x0"][k]
+            o = orc.solve(x, c0, orc.Params(C=p.C, m=p.m, eps=0.0, max_iter=(g + 1) * steps),
+                          lam, xi, U0=U0)
+            assert out["fit_hist"][g, k] == o["J"]
+    k = int(np.argmin(out["fit_hist"].min(axis=0)))
+    lam, xi = st["x0"][k]
+    o = orc.solve(x, c0, orc.Params(C=p.C, m=p.m, eps=0.0, max_iter=4 * steps), lam, xi, U0=U0)
+    np.testing.assert_array_equal(out["U_best"], o["U"])
+    np.testing.assert_array_equal(out["c_best"], o["c"])
+
+
+def test_pso_interleaved_first_generation_is_the_plain_swarm(orc):
+    """Generation 0 starts every particle from (c0, U0): its fitnesses are the
+    plain swarm's with max_iter = steps, and the first move is the same."""
+    x, p, c0, U0, st = _pso_case(orc, P=5, G=2, seed=10)
+    steps = 3
+    a = orc.pso_interleaved(x, c0, U0, p, st, steps=steps)
+    b = orc.pso(x, c0, U0, orc.Params(C=p.C, m=p.m, eps=0.0, max_iter=steps), st)
+    np.testing.assert_array_equal(a["fit_hist"][0], b["fit_hist"][0])
+    np.testing.assert_array_equal(a["pos_hist"][1], b["pos_hist"][1])
+    # generation 1 continues from the carried states, so it differs from a
+    # fresh solve at the same particles
+    assert not np.array_equal(a["fit_hist"][1], b["fit_hist"][1])
+
+
+# ------------------------------------------------------------------ slab mode
+def _bruteforce_slab_step(x, U, c, lam, xi, zbeg, zend, m=2.0):
+    """One step in which only the planes [zbeg, zend) change: H and F from the
+    literal neighbourhood scan of the whole volume, eqs (4), (2) on the
+    active voxels, eq (3) and eq (1) summed over the active voxels."""
+    H, F = bruteforce_hf(x, U)
+    nz, ny, nx = x.shape
+    flat = np.asarray(x, np.float64).reshape(-1)
+    U = np.asarray(U, np.float64).reshape(flat.size, -1)
+    act = np.zeros((nz, ny, nx), bool)
+    act[zbeg:zend] = True
+    act = act.reshape(-1)
+    a = 1.0 - lam * H - xi * F
+    d2 = np.maximum((flat[:, None] - np.asarray(c)[None, :]) ** 2 * a, 1e-12)
+    J = float((U[act] ** m * d2[act]).sum())
+    w = (1.0 / d2) ** (1.0 / (m - 1.0))
+    Un = U.copy()
+    Un[act] = (w / w.sum(1, keepdims=True))[act]
+    um = Un[act] ** m
+    cn = (um * flat[act, None]).sum(0) / um.sum(0)
+    return Un, cn, J
+
+
+def test_slab_of_the_whole_volume_is_the_solve(orc):
+    rng = np.random.default_rng(21)
+    x = _rand_vol(rng, (4, 5, 6))
+    U0 = random_memberships(rng, x.size, 3)
+    p = orc.Params(C=3, m=2.0, eps=0.0, max_iter=4)
+    c0 = np.array([0.2, 0.5, 0.8])
+    a = orc.solve(x, c0, p, 0.3, 0.4, U0=U0)
+    b = orc.solve_slab(x, c0, p, 0.3, 0.4, U0, 0, 4)
+    np.testing.assert_array_equal(a["U"], b["U"])
+    np.testing.assert_array_equal(a["c"], b["c"])
+    assert a["J"] == b["J"]
+
+
+@pytest.mark.parametrize("zbeg,zend", [(0, 1), (2, 3), (4, 5), (1, 4)])
+def test_slab_matches_bruteforce_with_fixed_context(orc, zbeg, zend):
+    rng = np.random.default_rng(22 + zbeg)
+    x = _rand_vol(rng, (5, 4, 6))
+    U0 = random_memberships(rng, x.size, 3)
+    c0 = np.array([0.15, 0.5, 0.85])
+    lam, xi = 0.35, 0.25
+    U1, c1, J0 = _bruteforce_slab_step(x, U0, c0, lam, xi, zbeg, zend)
+    U2, c2, J1 = _bruteforce_slab_step(x, U1, c1, lam, xi, zbeg, zend)
+    o = orc.solve_slab(x, c0, orc.Params(C=3, m=2.0, eps=0.0, max_iter=2), lam, xi, U0, zbeg,
+                       zend, want_hist=True)
+    np.testing.assert_allclose(o["U"], U2, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(o["c"], c2, rtol=1e-13)
+    np.testing.assert_allclose(o["J_hist"], [J0, J1], rtol=1e-13)
+    # the context planes never change
+    keep = np.ones(x.shape, bool)
+    keep[zbeg:zend] = False
+    np.testing.assert_array_equal(o["U"][keep.reshape(-1)], U0[keep.reshape(-1)])

@@ -142,3 +142,46 @@ def test_tune_keeps_results_and_reports_choice(ctx):
                      float(parts[2, 0]), float(parts[2, 1]), U0=host(U0[0]).astype(np.float64))
     assert abs(after["fitness"][0, 2] - o["J"]) <= TOL * abs(o["J"])
     assert rel(after["centres"][0, 2], o["c"]) <= TOL
+
+
+def test_pso_interleaved_matches_oracle(ctx):
+    """Particles carrying their own state, 2 iterations per generation."""
+    from gpu_util import rel2, saturated
+    xo, xg = _volume(ctx, (10, 24, 30), 70)
+    c0, U0, _ = oracle.fcm_init(xo, oracle.Params(C=4, m=2.0, eps=0.0, max_iter=10))
+    c0, U0 = c0.astype(np.float32), U0.astype(np.float32)
+    st = synth.pso_streams(127, 6, 4)
+    o = oracle.pso_interleaved(xo, c0.astype(np.float64), U0.astype(np.float64),
+                               oracle.Params(C=4, m=2.0), st, steps=2)
+    assert pso_replay(o["fit_hist"], st)[3] > 1e-3
+    g = ctx.pifcm_pso_interleaved([xg], _P(C=4, m=2.0), st, c0[None], [dev(U0)], steps=2)
+    assert np.max(np.abs(g["pos_hist"][0] - o["pos_hist"])) <= 1e-12
+    assert rel(g["fit_hist"][0], o["fit_hist"]) <= TOL
+    assert np.max(np.abs(g["best_pos"][0] - o["best_pos"])) <= 1e-12
+    sat = saturated(*o["best_pos"])
+    assert (rel2 if sat else rel)(host(g["U_best"][0]), o["U_best"]) <= TOL
+    assert rel(g["centres_best"][0], o["c_best"]) <= TOL
+
+
+def test_pso_interleaved_frozen_swarm_equals_long_solves(ctx):
+    from paper_2002_01981_amd import PIFCM_SWARM_PLAIN
+    xs, c0, U0 = _multi(ctx, [(7, 19, 33), (5, 12, 40)], 76)
+    st = synth.pso_streams(128, 3, 3)
+    st = dict(x0=st["x0"], v0=np.zeros_like(st["v0"]), r1=np.zeros_like(st["r1"]),
+              r2=np.zeros_like(st["r2"]))
+    steps = 2
+    g = ctx.pifcm_pso_interleaved(xs, _P(C=4, m=2.0), st, c0, U0, steps=steps)
+    gp = ctx.pifcm_pso_interleaved(xs, _P(C=4, m=2.0), st, c0, U0, steps=steps,
+                                   mode=PIFCM_SWARM_PLAIN)
+    assert np.array_equal(g["fit_hist"], gp["fit_hist"])
+    parts = st["x0"].astype(np.float32)
+    for gen in range(3):
+        ev = ctx.swarm_evaluate(xs, _P(C=4, m=2.0, eps=0.0, max_iter=(gen + 1) * steps), parts,
+                                c0, U0)
+        assert np.array_equal(ev["fitness"], g["fit_hist"][:, gen])
+    for b in range(2):
+        k = int(np.argmin(g["fit_hist"][b].min(axis=0)))
+        s = ctx.ifcm_solve(xs[b], _P(C=4, m=2.0, eps=0.0, max_iter=3 * steps), float(parts[k, 0]),
+                           float(parts[k, 1]), c0[b], U_in=U0[b])
+        assert np.array_equal(host(s["U"]), host(g["U_best"][b]))
+        assert np.array_equal(s["c"], g["centres_best"][b])

@@ -131,3 +131,32 @@ def test_ring_limits(ctx):
     with pytest.raises(PifcmError) as e:
         ctx.ifcm_backward(x, _P(C=4, V=2), 0.3, 0.3, c0, U0, 3, 1)
     assert e.value.status == PIFCM_E_UNSUPPORTED
+
+
+def test_confusion_counts_exact(ctx):
+    """pifcm_confusion against numpy on random labels (integer counts: bit
+    exact), and the FCM segmentation of the nested phantom against its
+    classes."""
+    import torch
+    from paper_2002_01981_amd import PifcmError
+    from paper_2002_01981_amd.quality import misclassification
+    rng = np.random.default_rng(5)
+    for n, C, K in ((1, 2, 2), (1000, 4, 4), (300001, 16, 5)):
+        lab = rng.integers(0, C, n).astype(np.uint8)
+        tru = rng.integers(0, K, n).astype(np.uint8)
+        got = ctx.pifcm_confusion(dev(lab), dev(tru), C, K)
+        ref = np.zeros((C, K), np.int64)
+        np.add.at(ref, (lab.astype(int), tru.astype(int)), 1)
+        assert np.array_equal(got, ref)
+    with pytest.raises(PifcmError):
+        ctx.pifcm_confusion(dev(np.array([0, 4], np.uint8)), dev(np.array([0, 1], np.uint8)), 4, 4)
+    raw, truth = synth.nested_ellipsoids(shape=(8, 32, 32), seed=1, sigma=0.05)
+    x = ctx.pifcm_normalize(dev(raw))
+    c0, U0, _ = ctx.pifcm_fcm_init(x, _P(C=4, m=2.0, eps=1e-5, max_iter=50))
+    fin = ctx.ifcm_solve(x, _P(C=4, m=2.0, eps=1e-5, max_iter=50), 0.0, 0.0, c0, U_in=U0,
+                         labels=True)
+    counts = ctx.pifcm_confusion(fin["labels"], dev(truth.reshape(-1)), 4, 4)
+    ref = np.mean(host(fin["labels"]) != truth.reshape(-1))
+    assert abs(misclassification(counts) - ref) < 1e-15
+    assert misclassification(counts) < 0.1
+    del torch
