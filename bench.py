@@ -244,6 +244,11 @@ def main():
 
     plain = None
     if not args.no_plain and mode == PIFCM_SWARM_BATCHED:
+        # the plain mode runs one small launch per (volume, particle): it gets
+        # a context of its own with the default decomposition, not the tile
+        # shape tuned for the batched launch
+        ctx_b = ctx
+        ctx = Context(0)
         step(PIFCM_SWARM_PLAIN)
         torch.cuda.synchronize()
         ctx.pifcm_set_timing(True)
@@ -253,13 +258,16 @@ def main():
         tp1 = time.perf_counter()
         ctx.pifcm_set_timing(False)
         pk_ms, pl = ctx.pifcm_get_timing(reset=True)
-        same = bool(np.array_equal(outp["fitness"], out["fitness"]))
+        same = float(np.max(np.abs(outp["fitness"] / out["fitness"] - 1.0)))
+        ctx.close()
+        ctx = ctx_b
         plain = dict(ms_per_step=round((tp1 - tp0) * 1e3, 3),
                      value=work / (tp1 - tp0), launches_per_step=int(pl),
                      avg_launch_us=round(pk_ms / max(pl, 1) * 1e3, 2),
                      batched_speedup=round((tp1 - tp0) * 1e3 / ms_step, 3),
-                     bit_identical_to_batched=same)
-        log(f"plain: {(tp1 - tp0) * 1e3:.1f} ms/step, identical={same}")
+                     max_rel_fitness_diff_vs_batched=same,
+                     decomposition="default (4 waves x 32 planes)")
+        log(f"plain: {(tp1 - tp0) * 1e3:.1f} ms/step, max rel diff {same:.2e}")
 
     ring = None
     if not args.no_ring:
