@@ -219,7 +219,9 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
     // eqs (5)/(7) ratios, (4), (1), (2), (3).
     auto finalize = [&](int z, auto Sc, int bz) __attribute__((always_inline)) {
       constexpr int S = decltype(Sc)::value;
-      if (!active) return;
+      // Computed by every lane (a lane outside the volume sees staged zeros
+      // and finite distances); only its store and its sums are masked, so no
+      // conditional block holds the arithmetic.
       const float xv = sx_at(bz, 0, 0);
       float uo[C];
       su_at(bz, 0, 0, uo);
@@ -246,14 +248,14 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
         float un[C];
         memberships<C, M2>(d2, a.m, un);  // eq (2)
         const uint32_t ob = ((uint32_t)(z - zb) * psz + own_xy) * (4u * C);
-        store_row<C>(at_byte(Ob, ob), un);
+        if (active) store_row<C>(at_byte(Ob, ob), un);
 #pragma unroll
         for (int j = 0; j < C; ++j) {
-          const float w = pow_m<M2>(un[j], a.m);
+          const float w = active ? pow_m<M2>(un[j], a.m) : 0.f;
           acc[j] = fmaf(w, xv, acc[j]);  // eq (3) numerator
           acc[C + j] += w;                // eq (3) denominator
         }
-        acc[2 * C] += Jv;
+        acc[2 * C] += Jv;  // 0 for a lane outside: its staged memberships are 0
       } else {
         acc[0] += Jv;
       }
@@ -346,18 +348,34 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
 #pragma unroll
           for (int j = 0; j < C; ++j) fn[SC][j] = Sb[j];
         }
+        // The gathers are complete here: the compiler may not sink them past
+        // the staging below (which waits on the prefetch loads).
+#pragma unroll
+        for (int s2 = 0; s2 < 3; ++s2) {
+#pragma unroll
+          for (int j = 0; j < CH; ++j) asm volatile("" : "+v"(hn[s2][j]));
+#pragma unroll
+          for (int j = 0; j < C; ++j) asm volatile("" : "+v"(fn[s2][j]));
+        }
       } else if (doC) {
 #pragma unroll
         for (int j = 0; j < CH; ++j) hn[SC][j] = 0.f;
 #pragma unroll
         for (int j = 0; j < C; ++j) fn[SC][j] = 0.f;
       }
-      if (doA) finalize(p - 1, SAc, bprev);
+      // Stage plane p+1 and prefetch p+2 before finalising p-1: the global
+      // store of p-1's memberships then has a whole plane of work to drain
+      // before the next wait on the prefetch loads.  The fence keeps the
+      // staging (and its wait for the prefetch) after this plane's gathers.
+      __builtin_amdgcn_sched_barrier(0);
       if (!GEN || p + 1 <= zhi) {
         store_plane(bnext);
         gs[SC] = rg;
         if (!GEN || p + 2 <= zhi) load_plane(p + 2);
       }
+      if (doA) finalize(p - 1, SAc, bprev);
+      // Keep the next plane's gathers after this plane's store.
+      __builtin_amdgcn_sched_barrier(0);
     };
 
     // Canonical slot ring: slot 0 = voxel p-1, 1 = p, 2 = p+1.  After a plane
