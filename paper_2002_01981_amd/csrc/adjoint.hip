@@ -24,7 +24,7 @@
 // it, so a flat i contributes g = 1).  The objective-only pass at U^K starts
 // the chain with dJ/du_ij = m u_ij^(m-1) d_ij and dd_ij = u_ij^m.
 // k_adj_point does the per-voxel part (recomputing the forward values from
-// (U^t, c^t)), k_adj_transpose the gather of dU; per-block sums of dc,
+// (U^t, c^t)), k_adj_transpose_tiled the gather of dU; per-block sums of dc,
 // dlambda and dxi go to slots that k_adj_finalize adds in fp64.
 #include "common.h"
 #include "pifcm_kernels.h"
@@ -32,6 +32,7 @@
 namespace pifcm {
 
 constexpr int kAdjThreads = 256;
+constexpr int kAdjVoxPerThread = 1;  // voxels per thread of k_adj_point
 
 // Per-voxel stencil view of the 3x3x3 cube: coordinates from the linear
 // index (32-bit: volumes hold fewer than 2^32 voxels) and, per axis, whether
@@ -74,7 +75,6 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_point(const AdjArgs a) {
   constexpr int NV = C + 2;  // dc[C], dlambda, dxi
   __shared__ float s_red[(kAdjThreads / 64) * NV];
   const size_t N = (size_t)a.nx * a.ny * a.nz;
-  const size_t i = (size_t)blockIdx.x * kAdjThreads + threadIdx.x;
   const float m = a.m;
   float acc[NV];
 #pragma unroll
@@ -92,7 +92,10 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_point(const AdjArgs a) {
       dA[j] = dB[j] = 0.f;
     }
   }
-  if (i < N) {
+  // Each block covers kAdjVoxPerThread consecutive runs of kAdjThreads voxels.
+  for (int r = 0; r < kAdjVoxPerThread; ++r) {
+    const size_t i = ((size_t)blockIdx.x * kAdjVoxPerThread + r) * kAdjThreads + threadIdx.x;
+    if (i >= N) break;
     const Nbr nb(a.nx, a.ny, a.nz, i);
     const float xv = a.x[i];
     const float ig = a.invg[i];
@@ -205,50 +208,242 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_point(const AdjArgs a) {
   block_tile_store<NV, kAdjThreads>(pr, blockIdx.x, acc, s_red);
 }
 
+// The transpose gather on wave-private z-streaming tiles (the layout of the
+// fused forward step): a wave owns 16 x 4 columns of a tile of zc planes,
+// each plane of the tile plus a one-voxel halo is staged once in the wave's
+// LDS as (xc, P, Q) per cell -- xc the cell's intensity as the cell uses it
+// in eq (5) (shifted by -1 for a flat neighbourhood) -- and every lane adds
+// its 3 x 3 in-plane cells to the three voxels of its column they touch.
+// For the Q part the in-plane cells are summed per offset class first (the
+// weights of eq (7) depend only on the class).
+constexpr int kAdjTX = 16, kAdjTY = 4, kAdjHX = kAdjTX + 2, kAdjHY = kAdjTY + 2;
+constexpr int kAdjCells = kAdjHX * kAdjHY;   // 108 cells per staged plane
+constexpr int kAdjHalo = kAdjCells - 64;     // 44 halo cells, one per lane
+constexpr int kAdjZc = 64;                   // planes per tile
+// Waves per work group: as many (up to 4) as the staged planes of each wave
+// leave room for in LDS.
+template <int C>
+constexpr int adj_waves() { return C <= 12 ? 4 : 3; }
+
 template <int C, bool EVAL>
-__global__ __launch_bounds__(kAdjThreads) void k_adj_transpose(const AdjArgs a, float* Ubar_out) {
-  const size_t N = (size_t)a.nx * a.ny * a.nz;
-  const size_t k = (size_t)blockIdx.x * kAdjThreads + threadIdx.x;
-  if (k >= N) return;
-  const Nbr nb(a.nx, a.ny, a.nz, k);
-  const float xk = a.x[k];
-  float u[C], out[C];
-  load_row<C>(as_global(a.U) + k * C, u);
-  if constexpr (EVAL) load_row<C>(as_global(a.Ubar_direct) + k * C, out);
-  else {
+__global__ __launch_bounds__(64 * adj_waves<C>()) void k_adj_transpose_tiled(const AdjArgs a, float* Ubar_out) {
+  constexpr int kAdjWaves = adj_waves<C>();
+  constexpr int CP = (C + 3) / 4 * 4;
+  constexpr int CW = 4 + 2 * CP;             // floats per staged cell: xc (+3 pad), P, Q
+  __shared__ __align__(16) float s_c[kAdjWaves][3][kAdjCells * CW];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tx = lane & (kAdjTX - 1), ty = lane / kAdjTX;
+  const int own_cell = (ty + 1) * kAdjHX + (tx + 1);
+  int hcx, hcy;
+  if (lane < kAdjHX) { hcy = 0; hcx = lane; }
+  else if (lane < 2 * kAdjHX) { hcy = kAdjHY - 1; hcx = lane - kAdjHX; }
+  else if (lane < 2 * kAdjHX + kAdjTY) { hcy = 1 + lane - 2 * kAdjHX; hcx = 0; }
+  else { hcy = 1 + lane - 2 * kAdjHX - kAdjTY; hcx = kAdjHX - 1; }
+  const bool hlane = lane < kAdjHalo;
+  const int halo_cell = hlane ? hcy * kAdjHX + hcx : 0;
+  const float wCa = a.q2_sqdist ? 2.f : 4.f;  // in-plane corner (edge weighs 1)
+  const float wEb = a.q2_sqdist ? 2.f : 4.f, wCb = a.q2_sqdist ? 3.f : 9.f;  // off-plane
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int ntx = (nx + kAdjTX - 1) / kAdjTX, nty = (ny + kAdjTY - 1) / kAdjTY;
+  const int ntz = (nz + kAdjZc - 1) / kAdjZc;
+  const int nitems = ntx * nty * ntz;
+  const uint32_t psz = (uint32_t)nx * (uint32_t)ny;
+
+  const int per = (nitems + 7) >> 3;
+  const int xcd = blockIdx.x & 7;
+  const int it_end = min(nitems, (xcd + 1) * per);
+  const int it_step = (gridDim.x >> 3) * kAdjWaves;
+  for (int it = xcd * per + (blockIdx.x >> 3) * kAdjWaves + wave; it < it_end; it += it_step) {
+    const int txi = it % ntx;
+    const int rest = it / ntx;
+    const int tyi = rest % nty;
+    const int tzi = rest / nty;
+    const int x0 = txi * kAdjTX, y0 = tyi * kAdjTY;
+    const int zlo = tzi * kAdjZc, zhi = min(zlo + kAdjZc, nz);
+    const int gx = x0 + tx, gy = y0 + ty;
+    const bool active = gx < nx && gy < ny;
+    const int hx = x0 - 1 + hcx, hy = y0 - 1 + hcy;
+    const bool hvalid = hlane && hx >= 0 && hx < nx && hy >= 0 && hy < ny;
+    const size_t own_xy = active ? (size_t)gy * nx + gx : 0;
+    const size_t halo_xy = hvalid ? (size_t)hy * nx + hx : 0;
+    // eq (7) denominators do not enter here (they are folded into Q); the
+    // class weights do.
+    float* const sc = &s_c[wave][0][0];
+
+    // Prefetch registers of one plane: own and halo cell.
+    float rxc, rx, rp[2 * C], hxc, hp[2 * C];
+    auto load_plane = [&](int q) __attribute__((always_inline)) {
+      const bool pv = q >= 0 && q < nz;
+      if (pv && active) {
+        const size_t i = (size_t)q * psz + own_xy;
+        rx = a.x[i];
+        rxc = a.invg[i] < 0.f ? rx - 1.f : rx;
+        load_row<2 * C>(as_global(a.PQ) + i * (2 * C), rp);
+      } else {
+        rx = rxc = 0.f;
 #pragma unroll
-    for (int j = 0; j < C; ++j) out[j] = 0.f;
-  }
-#pragma unroll
-  for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        if ((dx | dy | dz) == 0 || !nb.valid(dx, dy, dz)) continue;
-        const size_t i = nb.at(k, dx, dy, dz);
-        const float igi = a.invg[i];
-        const float xci = igi < 0.f ? a.x[i] - 1.f : a.x[i];
-        const float g = fabsf(xci - xk);  // g_ik as voxel i uses it
-        const float q = qweight((dx != 0) + (dy != 0) + (dz != 0), a.q2_sqdist);
-        const gfloat* PQ = as_global(a.PQ) + i * (2 * C);
-#pragma unroll
-        for (int j = 0; j < C; ++j) out[j] = fmaf(PQ[j], g, fmaf(2.f * u[j] * PQ[C + j], q, out[j]));
+        for (int j = 0; j < 2 * C; ++j) rp[j] = 0.f;
       }
-  store_row<C>(as_global(Ubar_out) + k * C, out);
+      if (pv && hvalid) {
+        const size_t i = (size_t)q * psz + halo_xy;
+        const float xh = a.x[i];
+        hxc = a.invg[i] < 0.f ? xh - 1.f : xh;
+        load_row<2 * C>(as_global(a.PQ) + i * (2 * C), hp);
+      } else {
+        hxc = 0.f;
+#pragma unroll
+        for (int j = 0; j < 2 * C; ++j) hp[j] = 0.f;
+      }
+    };
+    auto store_cell = [&](float* cell, float xc, const float (&pq)[2 * C]) __attribute__((always_inline)) {
+      cell[0] = xc;
+      float P[C], Q[C];
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        P[j] = pq[j];
+        Q[j] = pq[C + j];
+      }
+      lds_cell_store<C, CP>(cell + 4, P);  // offset 4 keeps the float4s aligned
+      lds_cell_store<C, CP>(cell + 4 + CP, Q);
+    };
+    auto store_plane = [&](int buf) __attribute__((always_inline)) {
+      float* base = sc + buf * kAdjCells * CW;
+      store_cell(base + own_cell * CW, rxc, rp);
+      if (hlane) store_cell(base + halo_cell * CW, hxc, hp);
+    };
+
+    // Target slots (voxels p-1, p, p+1 of the lane's column): P-part and
+    // class-weighted Q sums, and the target's own intensity.
+    float hP[3][C], fQ[3][C], xt[3];
+#pragma unroll
+    for (int s2 = 0; s2 < 3; ++s2) {
+      xt[s2] = 0.f;
+#pragma unroll
+      for (int j = 0; j < C; ++j) hP[s2][j] = fQ[s2][j] = 0.f;
+    }
+    auto finalize = [&](int z, int S) __attribute__((always_inline)) {
+      if (!active) return;
+      const size_t k = (size_t)z * psz + own_xy;
+      float u[C], out[C];
+      load_row<C>(as_global(a.U) + k * C, u);
+      if constexpr (EVAL) load_row<C>(as_global(a.Ubar_direct) + k * C, out);
+      else {
+#pragma unroll
+        for (int j = 0; j < C; ++j) out[j] = 0.f;
+      }
+#pragma unroll
+      for (int j = 0; j < C; ++j) out[j] += hP[S][j] + 2.f * u[j] * fQ[S][j];
+      store_row<C>(as_global(Ubar_out) + k * C, out);
+    };
+
+    auto cell_at = [&](int buf, int dy, int dx) -> const float* {
+      return sc + (buf * kAdjCells + own_cell + dy * kAdjHX + dx) * CW;
+    };
+    auto plane = [&](int p, int SA, int SB, int SC) __attribute__((always_inline)) {
+      const int bp = (p - zlo + 1) % 3;
+      const int bnext = (p - zlo + 2) % 3;
+      const bool pv = p >= 0 && p < nz;
+      const bool doA = p - 1 >= zlo, doB = p >= zlo && p < zhi, doC = p + 1 < zhi;
+      __builtin_amdgcn_wave_barrier();
+      const float xA = xt[SA], xB = xt[SB], xC = rx;  // plain target intensities
+      float hC[C], E[C], Co[C], Pc[C];
+#pragma unroll
+      for (int j = 0; j < C; ++j) hC[j] = E[j] = Co[j] = Pc[j] = 0.f;
+      if (pv) {
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+          for (int dx = -1; dx <= 1; ++dx) {
+            const float* cell = cell_at(bp, dy, dx);
+            const float xc = cell[0];
+            float P[C], Q[C];
+            lds_cell_load<C, CP>(cell + 4, P);
+            lds_cell_load<C, CP>(cell + 4 + CP, Q);
+            const int n = (dx != 0) + (dy != 0);
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+              if (n == 0) Pc[j] = Q[j];
+              else if (n == 1) E[j] += Q[j];
+              else Co[j] += Q[j];
+            }
+            const float gA = fabsf(xc - xA), gC = fabsf(xc - xC);
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+              hP[SA][j] = fmaf(P[j], gA, hP[SA][j]);
+              hC[j] = fmaf(P[j], gC, hC[j]);
+            }
+            if (n != 0) {
+              const float gB = fabsf(xc - xB);
+#pragma unroll
+              for (int j = 0; j < C; ++j) hP[SB][j] = fmaf(P[j], gB, hP[SB][j]);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const float Sa = fmaf(wCa, Co[j], E[j]);
+        const float Sb = fmaf(wCb, Co[j], fmaf(wEb, E[j], Pc[j]));
+        fQ[SA][j] += Sb;
+        fQ[SB][j] += Sa;
+        hP[SC][j] = hC[j];
+        fQ[SC][j] = Sb;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (p + 1 <= zhi) {
+        store_plane(bnext);
+        xt[SC] = rx;
+        if (p + 2 <= zhi) load_plane(p + 2);
+      }
+      if (doA) finalize(p - 1, SA);
+      (void)doB;
+      (void)doC;
+      __builtin_amdgcn_sched_barrier(0);
+    };
+
+    load_plane(zlo - 1);
+    store_plane(0);
+    load_plane(zlo);
+    // Slot ring: rotating indices (runtime: the arrays stay in registers only
+    // through full unrolling of the three-plane body below).
+    int p = zlo - 1;
+    while (p <= zhi) {
+      if (p > zlo && p + 4 <= zhi) {
+        plane(p, 0, 1, 2);
+        plane(p + 1, 1, 2, 0);
+        plane(p + 2, 2, 0, 1);
+        p += 3;
+      } else {
+        plane(p, 0, 1, 2);
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+          hP[0][j] = hP[1][j];
+          hP[1][j] = hP[2][j];
+          fQ[0][j] = fQ[1][j];
+          fQ[1][j] = fQ[2][j];
+        }
+        xt[0] = xt[1];
+        xt[1] = xt[2];
+        p += 1;
+      }
+    }
+  }
 }
 
 // Fixed-order fp64 sum of the adjoint block slots: out[0..C) = dJ/dc (this
 // step), acc2[0..1] += dJ/dlambda, dJ/dxi.
 template <int C>
-__global__ __launch_bounds__(256) void k_adj_finalize(const float* parts, int nslots, double* out,
-                                                      double* acc2) {
+__global__ __launch_bounds__(1024) void k_adj_finalize(const float* parts, int nslots, double* out,
+                                                       double* acc2) {
   constexpr int NV = C + 2;
-  __shared__ double s_red[4 * NV];
+  constexpr int NWF = 1024 / 64;
+  __shared__ double s_red[NWF * NV];
   double d[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) d[k] = 0.0;
-  for (int s = threadIdx.x; s < nslots; s += 256) {
+#pragma unroll 4
+  for (int s = threadIdx.x; s < nslots; s += 1024) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) d[k] += (double)parts[(size_t)s * NV + k];
   }
@@ -268,7 +463,8 @@ __global__ __launch_bounds__(256) void k_adj_finalize(const float* parts, int ns
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      const double t = ((s_red[k] + s_red[NV + k]) + s_red[2 * NV + k]) + s_red[3 * NV + k];
+      double t = 0.0;
+      for (int w = 0; w < NWF; ++w) t += s_red[w * NV + k];
       if (k < C) out[k] = t;
       else acc2[k - C] += t;
     }
@@ -279,7 +475,7 @@ template <int C>
 static hipError_t launch_adj_c(const AdjArgs& a, bool m2, bool eval, float* Ubar_out,
                                double* cbar_out, double* acc2, hipStream_t s) {
   const size_t N = (size_t)a.nx * a.ny * a.nz;
-  const int grid = (int)((N + kAdjThreads - 1) / kAdjThreads);
+  const int grid = (int)adjoint_slots(N);
   if (eval) {
     if (m2) hipLaunchKernelGGL((k_adj_point<C, true, true>), dim3(grid), dim3(kAdjThreads), 0, s, a);
     else hipLaunchKernelGGL((k_adj_point<C, false, true>), dim3(grid), dim3(kAdjThreads), 0, s, a);
@@ -287,10 +483,29 @@ static hipError_t launch_adj_c(const AdjArgs& a, bool m2, bool eval, float* Ubar
     if (m2) hipLaunchKernelGGL((k_adj_point<C, true, false>), dim3(grid), dim3(kAdjThreads), 0, s, a);
     else hipLaunchKernelGGL((k_adj_point<C, false, false>), dim3(grid), dim3(kAdjThreads), 0, s, a);
   }
-  hipLaunchKernelGGL((k_adj_finalize<C>), dim3(1), dim3(256), 0, s, a.partials, grid, cbar_out, acc2);
+  hipLaunchKernelGGL((k_adj_finalize<C>), dim3(1), dim3(1024), 0, s, a.partials, grid, cbar_out, acc2);
   if (Ubar_out) {
-    if (eval) hipLaunchKernelGGL((k_adj_transpose<C, true>), dim3(grid), dim3(kAdjThreads), 0, s, a, Ubar_out);
-    else hipLaunchKernelGGL((k_adj_transpose<C, false>), dim3(grid), dim3(kAdjThreads), 0, s, a, Ubar_out);
+    // Tiled transpose: one wave per tile, a persistent grid of resident
+    // work groups (a multiple of 8, one share per XCD).
+    static int occ[2] = {0, 0};
+    int& o = occ[eval ? 1 : 0];
+    if (!o) {
+      const void* f = eval ? reinterpret_cast<const void*>(&k_adj_transpose_tiled<C, true>)
+                           : reinterpret_cast<const void*>(&k_adj_transpose_tiled<C, false>);
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, f, 64 * adj_waves<C>(), 0) != hipSuccess || o < 1) o = 1;
+    }
+    const long ntiles = (long)((a.nx + kAdjTX - 1) / kAdjTX) * ((a.ny + kAdjTY - 1) / kAdjTY) *
+                        ((a.nz + kAdjZc - 1) / kAdjZc);
+    const long want = (ntiles + adj_waves<C>() - 1) / adj_waves<C>();
+    const long resident = (long)o * std::max(1, a.num_cu);
+    long g = want <= 8 * resident ? (want + 7) / 8 * 8 : resident / 8 * 8;
+    g = std::max<long>(8, g);
+    if (eval)
+      hipLaunchKernelGGL((k_adj_transpose_tiled<C, true>), dim3((int)g), dim3(64 * adj_waves<C>()), 0, s, a,
+                         Ubar_out);
+    else
+      hipLaunchKernelGGL((k_adj_transpose_tiled<C, false>), dim3((int)g), dim3(64 * adj_waves<C>()), 0, s, a,
+                         Ubar_out);
   }
   return hipGetLastError();
 }
@@ -309,6 +524,9 @@ hipError_t launch_adjoint(int C, const AdjArgs& a, bool m2, bool eval, float* Ub
   }
 }
 
-size_t adjoint_slots(size_t N) { return (N + kAdjThreads - 1) / kAdjThreads; }
+size_t adjoint_slots(size_t N) {
+  const size_t per = (size_t)kAdjThreads * kAdjVoxPerThread;
+  return (N + per - 1) / per;
+}
 
 }  // namespace pifcm

@@ -1097,6 +1097,7 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
   ad.xi = xi;
   ad.PQ = (float*)ctx->adj_pq.p;
   ad.partials = adj_parts;
+  ad.num_cu = ctx->num_cu;
   // The objective at the final state.
   ad.U = UK;
   ad.c = c_hist + (size_t)K * C;

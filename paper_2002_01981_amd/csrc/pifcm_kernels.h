@@ -51,6 +51,7 @@ struct AdjArgs {
   float* PQ;               // [N][2C] transpose sources
   float* Ubar_direct;      // [N][C] direct term of the objective-only pass
   float* partials;         // [blocks][C + 2]
+  int32_t num_cu;          // compute units of the device (grid sizing)
 };
 // Reverse of one iteration (eval = false) or of the final objective (eval =
 // true): writes dJ/dc of that state to cbar_out[C], adds dJ/dlambda and
