@@ -48,3 +48,20 @@ def test_product_does_not_reference_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "pifcm_oracle" not in text and "liboracle" not in text, f
+
+
+def test_build_entry_reaches_both_build_functions(monkeypatch):
+    """__graft_entry__.build() calls the oracle's and the library's build
+    functions (stubbed here so that nothing is compiled)."""
+    import importlib
+    import sys
+
+    sys.path.insert(0, ROOT)
+    entry = importlib.import_module("__graft_entry__")
+    calls = []
+    monkeypatch.setattr(importlib.import_module("oracle.build"), "build",
+                        lambda *a, **k: calls.append("oracle"))
+    monkeypatch.setattr(importlib.import_module("paper_2002_01981_amd.build"), "build",
+                        lambda *a, **k: calls.append("lib"))
+    entry.build()
+    assert calls == ["oracle", "lib"]
