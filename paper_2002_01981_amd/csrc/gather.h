@@ -403,20 +403,24 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
     load_plane(zlo - 1);
     store_plane(0);
     load_plane(zlo);
+    // The tile's first two planes, the interior in groups of three, the
+    // rest.  Three loops rather than one, so the interior loop's back edge
+    // carries the slots in the registers they entered with (no copies).
     int p = zlo - 1;
-    while (p <= zhi) {
-      if (p > zlo && p + 4 <= zhi) {
-        // Three interior planes (always entered at p = zlo + 1 + 3k, whose
-        // plane sits in buffer 2): every test is true, slots rotate by name.
-        plane(p, I0{}, I1{}, I2{}, I2{}, Steady{});
-        plane(p + 1, I1{}, I2{}, I0{}, I0{}, Steady{});
-        plane(p + 2, I2{}, I0{}, I1{}, I1{}, Steady{});
-        p += 3;
-      } else {
-        plane(p, I0{}, I1{}, I2{}, Bdyn{}, Gen{});
-        shift();
-        p += 1;
-      }
+    for (; p <= zlo && p <= zhi; ++p) {
+      plane(p, I0{}, I1{}, I2{}, Bdyn{}, Gen{});
+      shift();
+    }
+    // Interior planes (entered at p = zlo + 1 + 3k, whose plane sits in
+    // buffer 2): every test is true, slots rotate by name.
+    for (; p + 4 <= zhi; p += 3) {
+      plane(p, I0{}, I1{}, I2{}, I2{}, Steady{});
+      plane(p + 1, I1{}, I2{}, I0{}, I0{}, Steady{});
+      plane(p + 2, I2{}, I0{}, I1{}, I1{}, Steady{});
+    }
+    for (; p <= zhi; ++p) {
+      plane(p, I0{}, I1{}, I2{}, Bdyn{}, Gen{});
+      shift();
     }
 
     wave_tile_store<NV>(pr, tile, acc);
