@@ -24,61 +24,61 @@
 // it, so a flat i contributes g = 1).  The objective-only pass at U^K starts
 // the chain with dJ/du_ij = m u_ij^(m-1) d_ij and dd_ij = u_ij^m.
 // k_adj_point does the per-voxel part (recomputing the forward values from
-// (U^t, c^t)), k_adj_transpose_tiled the gather of dU; per-block sums of dc,
-// dlambda and dxi go to slots that k_adj_finalize adds in fp64.
+// (U^t, c^t)), k_adj_transpose_tiled the gather of dU; the sums of dc,
+// dlambda and dxi go to per-wave slots that k_adj_finalize adds in fp64.
 #include "common.h"
 #include "pifcm_kernels.h"
 
 namespace pifcm {
 
-constexpr int kAdjThreads = 256;
-constexpr int kAdjVoxPerThread = 1;  // voxels per thread of k_adj_point
+// Tiles of both tiled adjoint kernels: a wave owns 16 x 4 columns of a tile
+// of kAdjZc planes and walks it along z; each plane plus a one-voxel halo is
+// staged once in the wave's LDS.
+constexpr int kAdjTX = 16, kAdjTY = 4, kAdjHX = kAdjTX + 2, kAdjHY = kAdjTY + 2;
+constexpr int kAdjCells = kAdjHX * kAdjHY;   // 108 cells per staged plane
+constexpr int kAdjHalo = kAdjCells - 64;     // 44 halo cells, one per lane
+constexpr int kAdjZc = 64;                   // planes per tile
+// Waves per work group: as many (up to 4) as the staged planes of each wave
+// leave room for in LDS.
+constexpr int kAdjPW = 4;                    // waves per work group of k_adj_point
 
-// Per-voxel stencil view of the 3x3x3 cube: coordinates from the linear
-// index (32-bit: volumes hold fewer than 2^32 voxels) and, per axis, whether
-// the -1 and +1 neighbours exist.
-struct Nbr {
-  int nx, ny, nz;
-  int gx, gy, gz;
-  bool vxm, vxp, vym, vyp, vzm, vzp;
-  __device__ __forceinline__ Nbr(int nx_, int ny_, int nz_, size_t i) : nx(nx_), ny(ny_), nz(nz_) {
-    const uint32_t ii = (uint32_t)i;
-    gx = (int)(ii % (uint32_t)nx);
-    const uint32_t r = ii / (uint32_t)nx;
-    gy = (int)(r % (uint32_t)ny);
-    gz = (int)(r / (uint32_t)ny);
-    vxm = gx > 0;
-    vxp = gx < nx - 1;
-    vym = gy > 0;
-    vyp = gy < ny - 1;
-    vzm = gz > 0;
-    vzp = gz < nz - 1;
-  }
-  // Neighbour (dx, dy, dz) exists (offsets are compile-time constants).
-  __device__ __forceinline__ bool valid(int dx, int dy, int dz) const {
-    return (dx < 0 ? vxm : (dx > 0 ? vxp : true)) && (dy < 0 ? vym : (dy > 0 ? vyp : true)) &&
-           (dz < 0 ? vzm : (dz > 0 ? vzp : true));
-  }
-  // Linear index of neighbour (dx, dy, dz) of voxel i.
-  __device__ __forceinline__ size_t at(size_t i, int dx, int dy, int dz) const {
-    return (size_t)((long long)i + ((long long)dz * ny + dy) * nx + dx);
-  }
-};
-
-// eq (7) weight of an offset with n non-zero components: n^2, or n.
-__device__ __forceinline__ float qweight(int n, bool q2_sqdist) {
-  return q2_sqdist ? (float)n : (float)(n * n);
-}
-
+// The per-voxel part of the adjoint of one iteration on wave-private
+// z-streaming tiles (the layout of the fused forward step): each plane of a
+// tile plus its halo is staged once in the wave's LDS as (x, U) per cell,
+// every lane adds its 3 x 3 in-plane cells to the H and F numerators of the
+// three voxels of its column the plane touches (for F by offset class first:
+// the weights of eq (7) depend only on the class), and a voxel whose three
+// planes are done is finalised: it recomputes the forward values of eqs (4),
+// (2) from (U^t, c^t) and applies the adjoint formulas above, writing its
+// transpose sources (P, Q) and adding its dJ/dc, dJ/dlambda, dJ/dxi terms to
+// the lane's sums.  Each wave leaves its sums in its own slot.
 template <int C, bool M2, bool EVAL>
-__global__ __launch_bounds__(kAdjThreads) void k_adj_point(const AdjArgs a) {
-  constexpr int NV = C + 2;  // dc[C], dlambda, dxi
-  __shared__ float s_red[(kAdjThreads / 64) * NV];
-  const size_t N = (size_t)a.nx * a.ny * a.nz;
+__global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
+  constexpr int CP = (C + 3) / 4 * 4;
+  constexpr int CW = 4 + CP;   // floats per staged cell: x (+3 pad), U
+  constexpr int NV = C + 2;    // dc[C], dlambda, dxi
+  __shared__ __align__(16) float s_c[kAdjPW][3][kAdjCells * CW];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tx = lane & (kAdjTX - 1), ty = lane / kAdjTX;
+  const int own_cell = (ty + 1) * kAdjHX + (tx + 1);
+  int hcx, hcy;
+  if (lane < kAdjHX) { hcy = 0; hcx = lane; }
+  else if (lane < 2 * kAdjHX) { hcy = kAdjHY - 1; hcx = lane - kAdjHX; }
+  else if (lane < 2 * kAdjHX + kAdjTY) { hcy = 1 + lane - 2 * kAdjHX; hcx = 0; }
+  else { hcy = 1 + lane - 2 * kAdjHX - kAdjTY; hcx = kAdjHX - 1; }
+  const bool hlane = lane < kAdjHalo;
+  const int halo_cell = hlane ? hcy * kAdjHX + hcx : 0;
+  // eq (7) weights by offset class (in-plane edge and off-plane centre weigh 1).
+  const float wCa = a.q2_sqdist ? 2.f : 4.f;
+  const float wEb = a.q2_sqdist ? 2.f : 4.f, wCb = a.q2_sqdist ? 3.f : 9.f;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int ntx = (nx + kAdjTX - 1) / kAdjTX, nty = (ny + kAdjTY - 1) / kAdjTY;
+  const int ntz = (nz + kAdjZc - 1) / kAdjZc;
+  const int nitems = ntx * nty * ntz;
+  const uint32_t psz = (uint32_t)nx * (uint32_t)ny;
   const float m = a.m;
-  float acc[NV];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) acc[k] = 0.f;
+
   // Scalars of the adjoint of eq (3) for this step.
   float dA[C], dB[C], cj[C];
 #pragma unroll
@@ -92,120 +92,271 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_point(const AdjArgs a) {
       dA[j] = dB[j] = 0.f;
     }
   }
-  // Each block covers kAdjVoxPerThread consecutive runs of kAdjThreads voxels.
-  for (int r = 0; r < kAdjVoxPerThread; ++r) {
-    const size_t i = ((size_t)blockIdx.x * kAdjVoxPerThread + r) * kAdjThreads + threadIdx.x;
-    if (i >= N) break;
-    const Nbr nb(a.nx, a.ny, a.nz, i);
-    const float xv = a.x[i];
-    const float ig = a.invg[i];
-    const float gi = fabsf(ig);
-    const float xc = ig < 0.f ? xv - 1.f : xv;
-    float Gn[C], Fn[C];
+  float acc[NV];
 #pragma unroll
-    for (int j = 0; j < C; ++j) Gn[j] = Fn[j] = 0.f;
-    float qs = 0.f;
+  for (int k = 0; k < NV; ++k) acc[k] = 0.f;
+
+  const int per = (nitems + 7) >> 3;
+  const int xcd = blockIdx.x & 7;
+  const int it_end = min(nitems, (xcd + 1) * per);
+  const int it_step = (gridDim.x >> 3) * kAdjPW;
+  for (int it = xcd * per + (blockIdx.x >> 3) * kAdjPW + wave; it < it_end; it += it_step) {
+    const int txi = it % ntx;
+    const int rest = it / ntx;
+    const int tyi = rest % nty;
+    const int tzi = rest / nty;
+    const int x0 = txi * kAdjTX, y0 = tyi * kAdjTY;
+    const int zlo = tzi * kAdjZc, zhi = min(zlo + kAdjZc, nz);
+    const int gx = x0 + tx, gy = y0 + ty;
+    const bool active = gx < nx && gy < ny;
+    const int hx = x0 - 1 + hcx, hy = y0 - 1 + hcy;
+    const bool hvalid = hlane && hx >= 0 && hx < nx && hy >= 0 && hy < ny;
+    const size_t own_xy = active ? (size_t)gy * nx + gx : 0;
+    const size_t halo_xy = hvalid ? (size_t)hy * nx + hx : 0;
+    float* const sc = &s_c[wave][0][0];
+
+    // Denominator of eq (7) from the column position and the number of
+    // existing off-planes (0, 1, 2).
+    float invQ0, invQ1, invQ2;
+    {
+      const int ex = (gx > 0) + (gx < nx - 1), ey = (gy > 0) + (gy < ny - 1);
+      const float e = (float)(ex + ey), co = (float)(ex * ey);
+      const float q0 = e + wCa * co, q1 = 1.f + wEb * e + wCb * co;
+      invQ0 = q0 > 0.f ? 1.f / q0 : 0.f;
+      invQ1 = 1.f / (q0 + q1);
+      invQ2 = 1.f / (q0 + 2.f * q1);
+    }
+
+    // Prefetch registers of one plane: own cell (x, g_inv, U) and halo cell.
+    float rx, rg, ru[C], hxv, hu[C];
+    auto load_plane = [&](int q) __attribute__((always_inline)) {
+      const bool pv = q >= 0 && q < nz;
+      if (pv && active) {
+        const size_t i = (size_t)q * psz + own_xy;
+        rx = a.x[i];
+        rg = a.invg[i];
+        load_row<C>(as_global(a.U) + i * C, ru);
+      } else {
+        rx = 0.f;
+        rg = 1.f;
 #pragma unroll
-    for (int dz = -1; dz <= 1; ++dz)
+        for (int j = 0; j < C; ++j) ru[j] = 0.f;
+      }
+      if (pv && hvalid) {
+        const size_t i = (size_t)q * psz + halo_xy;
+        hxv = a.x[i];
+        load_row<C>(as_global(a.U) + i * C, hu);
+      } else {
+        hxv = 0.f;
 #pragma unroll
-      for (int dy = -1; dy <= 1; ++dy)
+        for (int j = 0; j < C; ++j) hu[j] = 0.f;
+      }
+    };
+    auto store_plane = [&](int buf) __attribute__((always_inline)) {
+      float* base = sc + buf * kAdjCells * CW;
+      base[own_cell * CW] = rx;
+      lds_cell_store<C, CP>(base + own_cell * CW + 4, ru);  // offset 4 keeps the float4s aligned
+      if (hlane) {
+        base[halo_cell * CW] = hxv;
+        lds_cell_store<C, CP>(base + halo_cell * CW + 4, hu);
+      }
+    };
+    auto cell_at = [&](int buf, int dy, int dx) -> const float* {
+      return sc + (buf * kAdjCells + own_cell + dy * kAdjHX + dx) * CW;
+    };
+
+    // Slots of the voxels p-1, p, p+1 of the lane's column: H and F
+    // numerators and the stored g_inv.
+    float hn[3][C], fn[3][C], gs[3];
 #pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          if ((dx | dy | dz) == 0 || !nb.valid(dx, dy, dz)) continue;
-          const size_t k = nb.at(i, dx, dy, dz);
-          const float g = fabsf(xc - a.x[k]);
-          const float q = qweight((dx != 0) + (dy != 0) + (dz != 0), a.q2_sqdist);
-          qs += q;
-          float u[C];
-          load_row<C>(as_global(a.U) + k * C, u);
+    for (int s2 = 0; s2 < 3; ++s2) {
+      gs[s2] = 1.f;
+#pragma unroll
+      for (int j = 0; j < C; ++j) hn[s2][j] = fn[s2][j] = 0.f;
+    }
+
+    auto finalize = [&](int z, int S, int bz) __attribute__((always_inline)) {
+      const float* own = cell_at(bz, 0, 0);
+      const float xv = own[0];
+      const float gi = fabsf(gs[S]);
+      const float iq = (z > 0 && z < nz - 1) ? invQ2 : ((z > 0 || z < nz - 1) ? invQ1 : invQ0);
+      float H[C], F[C], av[C], dd[C], e[C], d[C];
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        H[j] = hn[S][j] * gi;
+        F[j] = fn[S][j] * iq;
+        av[j] = 1.f - a.lam * H[j] - a.xi * F[j];
+        dd[j] = xv - cj[j];
+        e[j] = dd[j] * dd[j] * av[j];
+        d[j] = fmaxf(e[j], kDFloor);
+      }
+      const size_t i = (size_t)z * psz + own_xy;
+      float dbar[C];
+      if constexpr (EVAL) {
+        float u[C];
+        lds_cell_load<C, CP>(own + 4, u);
+        float direct[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+          const float um1 = M2 ? u[j] : (u[j] > 0.f ? exp2f((m - 1.f) * log2f(u[j])) : 0.f);
+          direct[j] = m * um1 * d[j];
+          dbar[j] = pow_m<M2>(u[j], m);
+        }
+        if (active) store_row<C>(as_global(a.Ubar_direct) + i * C, direct);
+      } else {
+        float w[C], up[C];
+        float sw = 0.f;
+        if constexpr (M2) {
 #pragma unroll
           for (int j = 0; j < C; ++j) {
-            Gn[j] = fmaf(u[j], g, Gn[j]);
-            Fn[j] = fmaf(u[j] * u[j], q, Fn[j]);
+            w[j] = 1.f / d[j];
+            sw += w[j];
+          }
+        } else {
+          float dmin = d[0];
+#pragma unroll
+          for (int j = 1; j < C; ++j) dmin = fminf(dmin, d[j]);
+          // w_j scaled by dmin^(1/(m-1)): s and dw scale alike, dd is unchanged.
+          const float ex = 1.f / (m - 1.f);
+#pragma unroll
+          for (int j = 0; j < C; ++j) {
+            w[j] = exp2f((log2f(dmin) - log2f(d[j])) * ex);
+            sw += w[j];
           }
         }
-    const float iq = qs > 0.f ? 1.f / qs : 0.f;
-    float H[C], F[C], av[C], dd[C], e[C], d[C];
+        const float is = 1.f / sw;
 #pragma unroll
-    for (int j = 0; j < C; ++j) {
-      H[j] = Gn[j] * gi;
-      F[j] = Fn[j] * iq;
-      av[j] = 1.f - a.lam * H[j] - a.xi * F[j];
-      dd[j] = xv - cj[j];
-      e[j] = dd[j] * dd[j] * av[j];
-      d[j] = fmaxf(e[j], kDFloor);
-    }
-    float dbar[C];
-    if constexpr (EVAL) {
-      float u[C];
-      load_row<C>(as_global(a.U) + i * C, u);
-      float direct[C];
+        for (int j = 0; j < C; ++j) up[j] = w[j] * is;
+        float gin[C];
+        if (active) load_row<C>(as_global(a.Ubar_next) + i * C, gin);
+        else {
 #pragma unroll
-      for (int j = 0; j < C; ++j) {
-        const float um1 = M2 ? u[j] : (u[j] > 0.f ? exp2f((m - 1.f) * log2f(u[j])) : 0.f);
-        direct[j] = m * um1 * d[j];
-        dbar[j] = pow_m<M2>(u[j], m);
-      }
-      store_row<C>(as_global(a.Ubar_direct) + i * C, direct);
-    } else {
-      float w[C], up[C];
-      float sw = 0.f;
-      if constexpr (M2) {
+          for (int j = 0; j < C; ++j) gin[j] = 0.f;
+        }
+        float dup[C];
+        float t = 0.f;
 #pragma unroll
         for (int j = 0; j < C; ++j) {
-          w[j] = 1.f / d[j];
-          sw += w[j];
+          const float um1 = M2 ? up[j] : (up[j] > 0.f ? exp2f((m - 1.f) * log2f(up[j])) : 0.f);
+          dup[j] = gin[j] + m * um1 * fmaf(dA[j], xv, dB[j]);
+          t = fmaf(dup[j], up[j], t);
         }
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+          const float dw = (dup[j] - t) * is;
+          dbar[j] = -dw * w[j] / ((m - 1.f) * d[j]);
+        }
+      }
+      float pq[2 * C];
+      const float keep = active ? 1.f : 0.f;
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const float de = e[j] > kDFloor ? dbar[j] * keep : 0.f;
+        const float da = de * dd[j] * dd[j];
+        acc[j] += -2.f * de * av[j] * dd[j];  // dJ/dc_j
+        acc[C] += -da * H[j];                // dJ/dlambda
+        acc[C + 1] += -da * F[j];            // dJ/dxi
+        pq[j] = -a.lam * da * gi;
+        pq[C + j] = -a.xi * da * iq;
+      }
+      if (active) store_row<2 * C>(as_global(a.PQ) + i * (2 * C), pq);
+    };
+
+    auto plane = [&](int p, int SA, int SB, int SC) __attribute__((always_inline)) {
+      const int bp = (p - zlo + 1) % 3;
+      const int bprev = (p - zlo + 3) % 3;  // plane p-1
+      const int bnext = (p - zlo + 2) % 3;
+      const bool pv = p >= 0 && p < nz;
+      const bool doA = p - 1 >= zlo, doB = p >= zlo && p < zhi, doC = p + 1 < zhi;
+      __builtin_amdgcn_wave_barrier();
+      // Centre values for g (shifted by -1 for a flat neighbourhood).
+      const float xA = doA ? cell_at(bprev, 0, 0)[0] : 0.f;
+      const float xcA = gs[SA] < 0.f ? xA - 1.f : xA;
+      const float xC = rg < 0.f ? rx - 1.f : rx;  // voxel p+1, prefetched
+      float hC[C], E[C], Co[C], Pc[C];
+#pragma unroll
+      for (int j = 0; j < C; ++j) hC[j] = E[j] = Co[j] = Pc[j] = 0.f;
+      if (pv) {
+        const float xB = cell_at(bp, 0, 0)[0];
+        const float xcB = gs[SB] < 0.f ? xB - 1.f : xB;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+          for (int dx = -1; dx <= 1; ++dx) {
+            const float* cell = cell_at(bp, dy, dx);
+            const float xk = cell[0];
+            float u[C];
+            lds_cell_load<C, CP>(cell + 4, u);
+            const int n = (dx != 0) + (dy != 0);
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+              if (n == 0) Pc[j] = u[j] * u[j];
+              else if (n == 1) E[j] = fmaf(u[j], u[j], E[j]);
+              else Co[j] = fmaf(u[j], u[j], Co[j]);
+            }
+            const float gA = fabsf(xcA - xk), gC = fabsf(xC - xk);  // eq (6)
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+              hn[SA][j] = fmaf(u[j], gA, hn[SA][j]);
+              hC[j] = fmaf(u[j], gC, hC[j]);
+            }
+            if (n != 0) {
+              const float gB = fabsf(xcB - xk);
+#pragma unroll
+              for (int j = 0; j < C; ++j) hn[SB][j] = fmaf(u[j], gB, hn[SB][j]);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const float Sa = fmaf(wCa, Co[j], E[j]);
+        const float Sb = fmaf(wCb, Co[j], fmaf(wEb, E[j], Pc[j]));
+        fn[SA][j] += Sb;
+        fn[SB][j] += Sa;
+        hn[SC][j] = hC[j];
+        fn[SC][j] = Sb;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (p + 1 <= zhi) {
+        store_plane(bnext);
+        gs[SC] = rg;
+        if (p + 2 <= zhi) load_plane(p + 2);
+      }
+      if (doA) finalize(p - 1, SA, bprev);
+      (void)doB;
+      (void)doC;
+      __builtin_amdgcn_sched_barrier(0);
+    };
+
+    load_plane(zlo - 1);
+    store_plane(0);
+    load_plane(zlo);
+    int p = zlo - 1;
+    while (p <= zhi) {
+      if (p > zlo && p + 4 <= zhi) {
+        plane(p, 0, 1, 2);
+        plane(p + 1, 1, 2, 0);
+        plane(p + 2, 2, 0, 1);
+        p += 3;
       } else {
-        float dmin = d[0];
-#pragma unroll
-        for (int j = 1; j < C; ++j) dmin = fminf(dmin, d[j]);
-        // w_j scaled by dmin^(1/(m-1)): s and dw scale alike, dd is unchanged.
-        const float ex = 1.f / (m - 1.f);
+        plane(p, 0, 1, 2);
 #pragma unroll
         for (int j = 0; j < C; ++j) {
-          w[j] = exp2f((log2f(dmin) - log2f(d[j])) * ex);
-          sw += w[j];
+          hn[0][j] = hn[1][j];
+          hn[1][j] = hn[2][j];
+          fn[0][j] = fn[1][j];
+          fn[1][j] = fn[2][j];
         }
-      }
-      const float is = 1.f / sw;
-#pragma unroll
-      for (int j = 0; j < C; ++j) up[j] = w[j] * is;
-      float gin[C];
-      load_row<C>(as_global(a.Ubar_next) + i * C, gin);
-      float dup[C];
-      float t = 0.f;
-#pragma unroll
-      for (int j = 0; j < C; ++j) {
-        const float um1 = M2 ? up[j] : (up[j] > 0.f ? exp2f((m - 1.f) * log2f(up[j])) : 0.f);
-        dup[j] = gin[j] + m * um1 * fmaf(dA[j], xv, dB[j]);
-        t = fmaf(dup[j], up[j], t);
-      }
-#pragma unroll
-      for (int j = 0; j < C; ++j) {
-        const float dw = (dup[j] - t) * is;
-        dbar[j] = -dw * w[j] / ((m - 1.f) * d[j]);
+        gs[0] = gs[1];
+        gs[1] = gs[2];
+        p += 1;
       }
     }
-    float pq[2 * C];
-#pragma unroll
-    for (int j = 0; j < C; ++j) {
-      const float de = e[j] > kDFloor ? dbar[j] : 0.f;
-      const float da = de * dd[j] * dd[j];
-      acc[j] += -2.f * de * av[j] * dd[j];  // dJ/dc_j
-      acc[C] += -da * H[j];                // dJ/dlambda
-      acc[C + 1] += -da * F[j];            // dJ/dxi
-      pq[j] = -a.lam * da * gi;
-      pq[C + j] = -a.xi * da * iq;
-    }
-    gfloat* PQ = as_global(a.PQ) + i * (2 * C);
-#pragma unroll
-    for (int j = 0; j < 2 * C; ++j) PQ[j] = pq[j];
   }
-  // Block sums (fixed order) into this block's slot.
   PairDev pr{};
   pr.partials = a.partials;
-  block_tile_store<NV, kAdjThreads>(pr, blockIdx.x, acc, s_red);
+  wave_tile_store<NV>(pr, blockIdx.x * kAdjPW + wave, acc);
 }
 
 // The transpose gather on wave-private z-streaming tiles (the layout of the
@@ -216,12 +367,6 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_point(const AdjArgs a) {
 // its 3 x 3 in-plane cells to the three voxels of its column they touch.
 // For the Q part the in-plane cells are summed per offset class first (the
 // weights of eq (7) depend only on the class).
-constexpr int kAdjTX = 16, kAdjTY = 4, kAdjHX = kAdjTX + 2, kAdjHY = kAdjTY + 2;
-constexpr int kAdjCells = kAdjHX * kAdjHY;   // 108 cells per staged plane
-constexpr int kAdjHalo = kAdjCells - 64;     // 44 halo cells, one per lane
-constexpr int kAdjZc = 64;                   // planes per tile
-// Waves per work group: as many (up to 4) as the staged planes of each wave
-// leave room for in LDS.
 template <int C>
 constexpr int adj_waves() { return C <= 12 ? 4 : 3; }
 
@@ -471,35 +616,57 @@ __global__ __launch_bounds__(1024) void k_adj_finalize(const float* parts, int n
   }
 }
 
+// Persistent grid of a tiled adjoint kernel with `waves` waves per work
+// group: one tile per wave while that fits in 8 rounds of the resident work
+// groups, else the resident work groups; a multiple of 8 (one share per
+// XCD), at least 8.
+static long adj_grid(const AdjArgs& a, int waves, int occ) {
+  const long ntiles = (long)((a.nx + kAdjTX - 1) / kAdjTX) * ((a.ny + kAdjTY - 1) / kAdjTY) *
+                      ((a.nz + kAdjZc - 1) / kAdjZc);
+  const long want = (ntiles + waves - 1) / waves;
+  const long resident = (long)std::max(occ, 1) * std::max(1, a.num_cu);
+  const long g = want <= 8 * resident ? (want + 7) / 8 * 8 : resident / 8 * 8;
+  return std::max<long>(8, g);
+}
+
+static int occupancy_of(const void* f, int threads) {
+  int o = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, f, threads, 0) != hipSuccess || o < 1) o = 1;
+  return o;
+}
+
 template <int C>
 static hipError_t launch_adj_c(const AdjArgs& a, bool m2, bool eval, float* Ubar_out,
                                double* cbar_out, double* acc2, hipStream_t s) {
-  const size_t N = (size_t)a.nx * a.ny * a.nz;
-  const int grid = (int)adjoint_slots(N);
-  if (eval) {
-    if (m2) hipLaunchKernelGGL((k_adj_point<C, true, true>), dim3(grid), dim3(kAdjThreads), 0, s, a);
-    else hipLaunchKernelGGL((k_adj_point<C, false, true>), dim3(grid), dim3(kAdjThreads), 0, s, a);
-  } else {
-    if (m2) hipLaunchKernelGGL((k_adj_point<C, true, false>), dim3(grid), dim3(kAdjThreads), 0, s, a);
-    else hipLaunchKernelGGL((k_adj_point<C, false, false>), dim3(grid), dim3(kAdjThreads), 0, s, a);
+  // Per-voxel part: each wave leaves its sums in slot (block, wave).
+  {
+    static int occ[4] = {0, 0, 0, 0};
+    const void* f = eval ? (m2 ? reinterpret_cast<const void*>(&k_adj_point<C, true, true>)
+                               : reinterpret_cast<const void*>(&k_adj_point<C, false, true>))
+                         : (m2 ? reinterpret_cast<const void*>(&k_adj_point<C, true, false>)
+                               : reinterpret_cast<const void*>(&k_adj_point<C, false, false>));
+    int& o = occ[(eval ? 2 : 0) + (m2 ? 1 : 0)];
+    if (!o) o = occupancy_of(f, 64 * kAdjPW);
+    const int g = (int)adj_grid(a, kAdjPW, o);
+    if (eval) {
+      if (m2) hipLaunchKernelGGL((k_adj_point<C, true, true>), dim3(g), dim3(64 * kAdjPW), 0, s, a);
+      else hipLaunchKernelGGL((k_adj_point<C, false, true>), dim3(g), dim3(64 * kAdjPW), 0, s, a);
+    } else {
+      if (m2) hipLaunchKernelGGL((k_adj_point<C, true, false>), dim3(g), dim3(64 * kAdjPW), 0, s, a);
+      else hipLaunchKernelGGL((k_adj_point<C, false, false>), dim3(g), dim3(64 * kAdjPW), 0, s, a);
+    }
+    hipLaunchKernelGGL((k_adj_finalize<C>), dim3(1), dim3(1024), 0, s, a.partials, g * kAdjPW, cbar_out,
+                       acc2);
   }
-  hipLaunchKernelGGL((k_adj_finalize<C>), dim3(1), dim3(1024), 0, s, a.partials, grid, cbar_out, acc2);
   if (Ubar_out) {
-    // Tiled transpose: one wave per tile, a persistent grid of resident
-    // work groups (a multiple of 8, one share per XCD).
+    // Tiled transpose: one wave per tile, a persistent grid.
     static int occ[2] = {0, 0};
     int& o = occ[eval ? 1 : 0];
-    if (!o) {
-      const void* f = eval ? reinterpret_cast<const void*>(&k_adj_transpose_tiled<C, true>)
-                           : reinterpret_cast<const void*>(&k_adj_transpose_tiled<C, false>);
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, f, 64 * adj_waves<C>(), 0) != hipSuccess || o < 1) o = 1;
-    }
-    const long ntiles = (long)((a.nx + kAdjTX - 1) / kAdjTX) * ((a.ny + kAdjTY - 1) / kAdjTY) *
-                        ((a.nz + kAdjZc - 1) / kAdjZc);
-    const long want = (ntiles + adj_waves<C>() - 1) / adj_waves<C>();
-    const long resident = (long)o * std::max(1, a.num_cu);
-    long g = want <= 8 * resident ? (want + 7) / 8 * 8 : resident / 8 * 8;
-    g = std::max<long>(8, g);
+    if (!o)
+      o = occupancy_of(eval ? reinterpret_cast<const void*>(&k_adj_transpose_tiled<C, true>)
+                            : reinterpret_cast<const void*>(&k_adj_transpose_tiled<C, false>),
+                       64 * adj_waves<C>());
+    const long g = adj_grid(a, adj_waves<C>(), o);
     if (eval)
       hipLaunchKernelGGL((k_adj_transpose_tiled<C, true>), dim3((int)g), dim3(64 * adj_waves<C>()), 0, s, a,
                          Ubar_out);
@@ -524,9 +691,13 @@ hipError_t launch_adjoint(int C, const AdjArgs& a, bool m2, bool eval, float* Ub
   }
 }
 
-size_t adjoint_slots(size_t N) {
-  const size_t per = (size_t)kAdjThreads * kAdjVoxPerThread;
-  return (N + per - 1) / per;
+// Upper bound of the slots k_adj_point writes (its grid never exceeds the
+// one-tile-per-wave grid, at least 8 work groups).
+size_t adjoint_slots(int nx, int ny, int nz) {
+  const long ntiles = (long)((nx + kAdjTX - 1) / kAdjTX) * ((ny + kAdjTY - 1) / kAdjTY) *
+                      ((nz + kAdjZc - 1) / kAdjZc);
+  const long want = (ntiles + kAdjPW - 1) / kAdjPW;
+  return (size_t)std::max<long>(8, (want + 7) / 8 * 8) * kAdjPW;
 }
 
 }  // namespace pifcm

@@ -1011,7 +1011,7 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
   // transpose sources, slots and small histories.
   const int nck = (K - 1) / S;
   const size_t hist_doubles = (size_t)(K + 1) * C * 2 + (size_t)K + 2;
-  const size_t adj_slots = adjoint_slots(N) * (C + 2);
+  const size_t adj_slots = adjoint_slots(vol->nx, vol->ny, vol->nz) * (C + 2);
   TRY(ensure(ctx, ctx->ubuf, 2 * UB, "memberships"));
   TRY(ensure(ctx, ctx->adj_ck, (size_t)std::max(nck, 1) * UB, "checkpoints"));
   TRY(ensure(ctx, ctx->adj_seg, (size_t)std::max(S - 1, 1) * UB, "segment states"));

@@ -50,7 +50,7 @@ struct AdjArgs {
   const double* B_next;    // eq (3) denominators of c^(t+1) [C]
   float* PQ;               // [N][2C] transpose sources
   float* Ubar_direct;      // [N][C] direct term of the objective-only pass
-  float* partials;         // [blocks][C + 2]
+  float* partials;         // [adjoint_slots][C + 2] per-wave sums
   int32_t num_cu;          // compute units of the device (grid sizing)
 };
 // Reverse of one iteration (eval = false) or of the final objective (eval =
@@ -58,7 +58,8 @@ struct AdjArgs {
 // dJ/dxi to acc2[0..1], and, if Ubar_out, dJ/dU of the state to Ubar_out.
 hipError_t launch_adjoint(int C, const AdjArgs& a, bool m2, bool eval, float* Ubar_out,
                           double* cbar_out, double* acc2, hipStream_t s);
-size_t adjoint_slots(size_t N);
+// Slots of per-wave sums the adjoint's per-voxel kernel writes (upper bound).
+size_t adjoint_slots(int nx, int ny, int nz);
 
 // Resident work groups per CU of the gather / pointwise kernels.
 int gather_occupancy(int C, int ty, bool m2, bool step);
