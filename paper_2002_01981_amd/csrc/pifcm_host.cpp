@@ -54,7 +54,7 @@ struct pifcm_ctx {
   std::string err;
   int num_cu = 256;
   DevBuf invg, ubuf, partials, states, jhist, tvol, tpair, flags;
-  DevBuf adj_ck, adj_seg, adj_bar, adj_pq, adj_misc;  // ifcm_backward workspace
+  DevBuf adj_ck, adj_seg, adj_bar, adj_pq, adj_misc, adj_rs;  // ifcm_backward workspace
   DevBuf tune_u0, tune_state;                          // pifcm_tune workspace
   DevBuf ring_tab;                                     // general-neighbourhood offsets
   DevBuf conf;                                         // pifcm_confusion counts
@@ -454,7 +454,8 @@ void pifcm_destroy(pifcm_ctx* ctx) {
   if (ctx->graph.graph) (void)hipGraphDestroy(ctx->graph.graph);
   for (DevBuf* b : {&ctx->invg, &ctx->ubuf, &ctx->partials, &ctx->states, &ctx->jhist, &ctx->tvol,
                     &ctx->tpair, &ctx->flags, &ctx->adj_ck, &ctx->adj_seg, &ctx->adj_bar,
-                    &ctx->adj_pq, &ctx->adj_misc, &ctx->tune_u0, &ctx->tune_state, &ctx->ring_tab, &ctx->conf, &ctx->pso_state})
+                    &ctx->adj_pq, &ctx->adj_misc, &ctx->adj_rs, &ctx->tune_u0, &ctx->tune_state, &ctx->ring_tab,
+                    &ctx->conf, &ctx->pso_state})
     if (b->p) (void)hipFree(b->p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
@@ -500,7 +501,7 @@ pifcm_status pifcm_workspace_bytes(pifcm_ctx* ctx, int64_t* device_bytes, int64_
   int64_t d = 0;
   for (const DevBuf* b : {&ctx->invg, &ctx->ubuf, &ctx->partials, &ctx->states, &ctx->jhist,
                           &ctx->tvol, &ctx->tpair, &ctx->flags, &ctx->adj_ck, &ctx->adj_seg,
-                          &ctx->adj_bar, &ctx->adj_pq, &ctx->adj_misc, &ctx->tune_u0,
+                          &ctx->adj_bar, &ctx->adj_pq, &ctx->adj_misc, &ctx->adj_rs, &ctx->tune_u0,
                           &ctx->tune_state, &ctx->ring_tab, &ctx->conf, &ctx->pso_state})
     d += (int64_t)b->cap;
   if (device_bytes) *device_bytes = d;
@@ -1022,8 +1023,17 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
   TRY(ensure(ctx, ctx->partials, (size_t)slots * (2 * C + 1) * sizeof(float), "tile sums"));
   TRY(ensure(ctx, ctx->states, 2 * sizeof(SolveState), "solve states"));
   TRY(ensure(ctx, ctx->jhist, (size_t)K * sizeof(double), "objective history"));
-  const size_t pin_need = (size_t)(S + 2) * (sizeof(SolveState) + sizeof(PairDev)) + sizeof(VolDev) +
-                          (size_t)(K + 1) * C * sizeof(float) + 64 * sizeof(double) + 4096;
+  // Every recomputed step of the backward pass gets its own state and pair
+  // record: R of them (S - 1 per full segment), uploaded in one copy.
+  int R = 0;
+  for (int t0 = 0; t0 < K; t0 += S) R += std::min(S, K - t0) - 1;
+  const size_t rs_states = ((size_t)std::max(R, 1) * sizeof(SolveState) + 255) / 256 * 256;
+  const size_t rs_bytes = rs_states + (size_t)std::max(R, 1) * sizeof(PairDev);
+  TRY(ensure(ctx, ctx->adj_rs, rs_bytes, "recompute states"));
+  const size_t pin_fixed = (size_t)(S + 2) * (sizeof(SolveState) + sizeof(PairDev)) + sizeof(VolDev) +
+                           (size_t)(K + 1) * C * sizeof(float) + 64 * sizeof(double) + 4096;
+  const size_t pin_rs = (pin_fixed + 255) / 256 * 256;  // pinned copy of the recompute records
+  const size_t pin_need = pin_rs + rs_bytes;
   TRY(ensure_pinned(ctx, pin_need));
   char* misc = (char*)ctx->adj_misc.p;
   float* adj_parts = (float*)misc;
@@ -1105,36 +1115,50 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
   HIPCHK(launch_adjoint(C, ad, m2, true, bar0, cbar + (size_t)K * C, acc2, ctx->s));
   float* cur = bar0;
   float* other = bar1;
-  // Recomputed states of the current segment: seg[i] = U^(t0 + i).
-  std::vector<const float*> seg(S, nullptr);
-  int seg_t0 = -1;
-  LaunchArgs a1 = make_args(ctx, (const VolDev*)ctx->tvol.p, tp + 1, vh, 1, 1, kind, p);
-  for (int t = K - 1; t >= 0; --t) {
-    const int t0 = (t / S) * S;
-    if (t0 != seg_t0) {
-      seg[0] = t0 == 0 ? U0 : ckpt(t0);
+  // Recomputed states of the current segment: seg[i] = U^(t0 + i), computed
+  // by one forward iteration U^(t0+i-1) -> U^(t0+i) with c^(t0+i-1) each.
+  // Their state and pair records are written once, here, and uploaded in one
+  // copy, so the reverse sweep below only enqueues work.
+  auto seg_state = [&](int i) -> float* { return (float*)((char*)ctx->adj_seg.p + (size_t)(i - 1) * UB); };
+  SolveState* rs_st = (SolveState*)ctx->adj_rs.p;
+  PairDev* rs_pr = (PairDev*)((char*)ctx->adj_rs.p + rs_states);
+  {
+    char* hrs = pin + pin_rs;
+    SolveState* hs_rs = (SolveState*)hrs;
+    PairDev* hp_rs = (PairDev*)(hrs + rs_states);
+    int r = 0;
+    for (int t0 = 0; t0 < K; t0 += S) {
       const int len = std::min(S, K - t0);
-      for (int i = 1; i < len; ++i) {
-        // One forward iteration U^(t0+i-1) -> U^(t0+i) with c^(t0+i-1).
-        char* slot = pin + (size_t)(i + 1) * (sizeof(SolveState) + sizeof(PairDev));
+      for (int i = 1; i < len; ++i, ++r) {
         pifcm_params p1 = *p;
         p1.eps = 0.f;
         p1.max_iter = 1;
-        SolveState s1 = init_state(&chost[(size_t)(t0 + i - 1) * C], C, lambda, xi, &p1, nullptr);
+        hs_rs[r] = init_state(&chost[(size_t)(t0 + i - 1) * C], C, lambda, xi, &p1, nullptr);
         PairDev q{};
-        q.U0 = seg[i - 1];
-        q.Ua = (float*)((char*)ctx->adj_seg.p + (size_t)(i - 1) * UB);
+        q.U0 = i == 1 ? (t0 == 0 ? U0 : ckpt(t0)) : seg_state(i - 1);
+        q.Ua = seg_state(i);
         q.Ub = q.Ua;
-        q.st = st_dev + 1;
+        q.st = rs_st + r;
         q.partials = (float*)ctx->partials.p;
-        std::memcpy(slot, &s1, sizeof s1);
-        std::memcpy(slot + sizeof(SolveState), &q, sizeof q);
-        HIPCHK(hipMemcpyAsync(st_dev + 1, slot, sizeof s1, hipMemcpyHostToDevice, ctx->s));
-        HIPCHK(hipMemcpyAsync(tp + 1, slot + sizeof(SolveState), sizeof q, hipMemcpyHostToDevice, ctx->s));
-        HIPCHK(launch_step(C, a1, grid, ts.nw, m2, kind, true, ctx->s));
-        seg[i] = q.Ua;
+        hp_rs[r] = q;
       }
-      HIPCHK(hipStreamSynchronize(ctx->s));  // pinned slots are reused by the next segment
+    }
+    if (R > 0) HIPCHK(hipMemcpyAsync(ctx->adj_rs.p, hrs, rs_bytes, hipMemcpyHostToDevice, ctx->s));
+  }
+  std::vector<const float*> seg(S, nullptr);
+  int seg_t0 = -1, seg_r = 0;
+  for (int t = K - 1; t >= 0; --t) {
+    const int t0 = (t / S) * S;
+    if (t0 != seg_t0) {
+      // First record of segment t0: the segments before it use t0 / S * (S - 1).
+      seg_r = (t0 / S) * (S - 1);
+      seg[0] = t0 == 0 ? U0 : ckpt(t0);
+      const int len = std::min(S, K - t0);
+      for (int i = 1; i < len; ++i) {
+        const LaunchArgs ar = make_args(ctx, (const VolDev*)ctx->tvol.p, rs_pr + seg_r + (i - 1), vh, 1, 1, kind, p);
+        HIPCHK(launch_step(C, ar, grid, ts.nw, m2, kind, true, ctx->s));
+        seg[i] = seg_state(i);
+      }
       seg_t0 = t0;
     }
     ad.U = seg[t - t0];
@@ -1146,7 +1170,7 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
     HIPCHK(launch_adjoint(C, ad, m2, false, t > 0 ? other : nullptr, cbar + (size_t)t * C, acc2, ctx->s));
     std::swap(cur, other);
   }
-  double* hout = (double*)(pin + pin_need - 64 * sizeof(double) - 4096);
+  double* hout = (double*)(pin + pin_fixed - 64 * sizeof(double) - 4096);
   HIPCHK(hipMemcpyAsync(hout, cbar, C * sizeof(double), hipMemcpyDeviceToHost, ctx->s));
   HIPCHK(hipMemcpyAsync(hout + C, acc2, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->s));
   HIPCHK(hipStreamSynchronize(ctx->s));
