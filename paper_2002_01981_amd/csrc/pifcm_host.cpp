@@ -317,7 +317,9 @@ int occupancy_of(int kind, int C, int nw, bool m2, bool step) {
 }
 
 // Work items in flight per work group.
-int items_per_group(int kind, int nw) { return kind == kGather ? nw : 1; }
+// Work items a work group takes at a time: one per wave for the tiled
+// kernels, one for the pointwise kernels.
+int items_per_group(int kind, int nw) { return kind == kGather ? nw : kind == kRing ? kRingWaves : 1; }
 
 // Offsets of the general neighbourhood (eq (9) up to the reach of V), sorted
 // by ring (Chebyshev shell, or squared distance with PIFCM_SHELL_SQDIST) with
@@ -390,7 +392,7 @@ LaunchArgs make_args(const pifcm_ctx* ctx, const VolDev* vols_dev, const PairDev
   a.P = P;
   a.q2_sqdist = (p->flags & PIFCM_Q2_SQDIST) ? 1 : 0;
   a.m = p->m;
-  a.use_1d = kind != kGather ? 1 : 0;
+  a.use_1d = kind == kFcm ? 1 : 0;  // the pointwise kernel's 1D tiles
   if (kind == kRing) {
     a.ring = (const RingOff*)ctx->ring_tab.p;
     a.nring = ctx->ring_n;

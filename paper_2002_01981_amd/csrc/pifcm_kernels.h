@@ -16,6 +16,8 @@ hipError_t launch_gather(int C, const LaunchArgs& a, int grid, int ty, bool m2, 
 hipError_t launch_finalize(int C, const LaunchArgs& a, int npairs, bool step, hipStream_t s);
 // Pointwise FCM step / objective (lambda = xi = 0).
 hipError_t launch_fcm(int C, const LaunchArgs& a, int grid, bool m2, bool step, hipStream_t s);
+// Waves (one tile each) per work group of the general-neighbourhood kernel.
+constexpr int kRingWaves = 4;
 // IFCM step / objective for general neighbourhoods (a.ring, a.W).
 hipError_t launch_ring(int C, const LaunchArgs& a, int grid, bool m2, bool step, hipStream_t s);
 int ring_occupancy(int C, bool m2, bool step);

@@ -1,32 +1,38 @@
 // ring.hip -- the IFCM step for general neighbourhoods: several rings with
 // the exponential weights of eq (10), or rings by squared distance.
 //
-// Each voxel (one thread) walks the offset table of the launch, which the
-// host sorts by ring.  Per ring r it forms the ratio of eq (5) (sum_k u_kj
-// g_ik over sum_k g_ik, or the mean of u_kj when every g_ik of the ring is
-// 0, or 0 for a ring without in-volume cells) and the ratio of eq (7), and
-// adds them with the weight W_r of eq (10).  Then eqs (4), (1), (2) and (3)
-// as in the fused 3x3x3 step.  Neighbours are read straight from global
-// memory (the caches hold the overlap between neighbouring voxels).
+// Each voxel walks the offset table of the launch, which the host sorts by
+// ring.  Per ring r it forms the ratio of eq (5) (sum_k u_kj g_ik over
+// sum_k g_ik, or the mean of u_kj when every g_ik of the ring is 0, or 0 for
+// a ring without in-volume cells) and the ratio of eq (7), and adds them with
+// the weight W_r of eq (10).  Then eqs (4), (1), (2) and (3) as in the fused
+// 3x3x3 step.  Work is decomposed like the fused step: a wave owns a tile of
+// 16 x 4 columns and zc planes and its lanes walk their columns along z, so
+// the cells a wave reads (its tile plus the reach of the table in x, y and
+// z) stay in the L1 cache while it moves one plane at a time; neighbours are
+// read from global memory through the caches.
 #include "common.h"
 #include "pifcm_kernels.h"
 
 namespace pifcm {
 
 template <int C, bool M2, bool STEP>
-__global__ __launch_bounds__(256) void k_ifcm_ring(const LaunchArgs a) {
-  constexpr int NT = 256;
+__global__ __launch_bounds__(64 * kRingWaves) void k_ifcm_ring(const LaunchArgs a) {
   constexpr int NV = STEP ? 2 * C + 1 : 1;
-  __shared__ float s_red[(NT / 64) * NV];
+  constexpr int TX = 16, TY = 4;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tx = lane & (TX - 1), ty = lane / TX;
   const int per = (a.nitems + 7) >> 3;
   const int xcd = blockIdx.x & 7;
   const int it_end = min(a.nitems, (xcd + 1) * per);
-  for (int it = xcd * per + (blockIdx.x >> 3); it < it_end; it += gridDim.x >> 3) {
+  const int it_step = (gridDim.x >> 3) * kRingWaves;
+  for (int it = xcd * per + (blockIdx.x >> 3) * kRingWaves + wave; it < it_end; it += it_step) {
     const int b = vol_of_item(a, it);
     const VolDev vd = ld_const(a.vols + b);
     const int r = it - a.item_begin[b];
-    const int pidx = r / vd.tiles1d;
-    const int tile = r - pidx * vd.tiles1d;
+    const int pidx = r / vd.tiles;
+    const int tile = r - pidx * vd.tiles;
     const PairDev pr = ld_const(a.pairs + b * a.P + pidx);
     const SolveState* st = pr.st;
     if (STEP && ld_const(&st->stop)) continue;
@@ -39,18 +45,18 @@ __global__ __launch_bounds__(256) void k_ifcm_ring(const LaunchArgs a) {
     for (int j = 0; j < C; ++j) cj[j] = ld_const(&st->c[(STEP ? t - 1 : t) & 1][j]);
     const float lam = ld_const(&st->lam), xi = ld_const(&st->xi);
     const int nx = vd.nx, ny = vd.ny, nz = vd.nz;
-    const size_t psz = (size_t)nx * ny;
-    const size_t N = (size_t)vd.zend * psz;  // end of the planes iterated
+    const int txi = tile % vd.ntx;
+    const int rest = tile / vd.ntx;
+    const int tyi = rest % vd.nty;
+    const int tzi = rest / vd.nty;
+    const int vx = txi * TX + tx, vy = tyi * TY + ty;
+    const bool active = vx < nx && vy < ny;
+    const int zlo = vd.zbeg + tzi * vd.zc, zhi = min(zlo + vd.zc, vd.zend);
     float acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.f;
-    const size_t base = (size_t)vd.zbeg * psz + (size_t)tile * NT * kFcmVoxPerThread;
-    for (int k = 0; k < kFcmVoxPerThread; ++k) {
-      const size_t i = base + (size_t)k * NT + threadIdx.x;
-      if (i >= N) break;
-      const int vx = (int)(i % (size_t)nx);
-      const size_t row = i / (size_t)nx;
-      const int vy = (int)(row % (size_t)ny), vz = (int)(row / (size_t)ny);
+    for (int vz = zlo; vz < zhi && active; ++vz) {
+      const size_t i = ((size_t)vz * ny + vy) * nx + vx;
       const float xv = X[i];
       float H[C], F[C];
 #pragma unroll
@@ -127,14 +133,14 @@ __global__ __launch_bounds__(256) void k_ifcm_ring(const LaunchArgs a) {
         acc[0] += Jv;
       }
     }
-    block_tile_store<NV, NT>(pr, tile, acc, s_red);
+    wave_tile_store<NV>(pr, tile, acc);
   }
 }
 
 template <int C, bool M2>
 static hipError_t launch_ring_ct(const LaunchArgs& a, int grid, bool step, hipStream_t s) {
-  if (step) hipLaunchKernelGGL((k_ifcm_ring<C, M2, true>), dim3(grid), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((k_ifcm_ring<C, M2, false>), dim3(grid), dim3(256), 0, s, a);
+  if (step) hipLaunchKernelGGL((k_ifcm_ring<C, M2, true>), dim3(grid), dim3(64 * kRingWaves), 0, s, a);
+  else hipLaunchKernelGGL((k_ifcm_ring<C, M2, false>), dim3(grid), dim3(64 * kRingWaves), 0, s, a);
   return hipGetLastError();
 }
 
@@ -143,7 +149,7 @@ static int occ_ring_ct(bool step) {
   int n = 0;
   const void* f = step ? reinterpret_cast<const void*>(&k_ifcm_ring<C, M2, true>)
                        : reinterpret_cast<const void*>(&k_ifcm_ring<C, M2, false>);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 256, 0) != hipSuccess) n = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64 * kRingWaves, 0) != hipSuccess) n = 1;
   return std::max(1, n);
 }
 
