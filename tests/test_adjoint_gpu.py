@@ -96,3 +96,20 @@ def test_gradient_brain_crop(ctx):
         Jo, go = _fd(x, c0, U0, 4, 2.0, lam, xi, 30)
         assert abs(Jg - Jo) <= 1e-4 * abs(Jo)
         assert np.max(np.abs(gg - go)) / np.max(np.abs(go)) <= GRAD_TOL, (lam, xi, gg, go)
+
+
+def test_gradient_flat_block_tiny_volume_and_more_clusters(ctx):
+    """A constant block inside a noisy volume (its interior voxels have flat
+    neighbourhoods: g_inv < 0, eq (5) becomes the mean), a volume smaller
+    than one wave tile in every direction, and C = 6."""
+    rng = np.random.default_rng(54)
+    raw, _ = synth.random_ellipsoids(shape=(7, 11, 13), seed=54, sigma=0.07)
+    raw[1:6, 2:8, 3:9] = 0.37
+    for raw_c, C, s in ((raw, 4, 3), (rng.random((3, 2, 5)).astype(np.float32), 3, 2), (raw, 6, 2)):
+        x = oracle.normalize(raw_c)
+        c0, U0, _ = oracle.fcm_init(x, oracle.Params(C=C, m=2.0, eps=0.0, max_iter=8))
+        c0, U0 = c0.astype(np.float32), U0.astype(np.float32)
+        Jg, gg = _gpu_grad(ctx, x, c0, U0, C, 2.0, 0.3, 0.25, 6, s)
+        Jo, go = _fd(x, c0, U0, C, 2.0, 0.3, 0.25, 6)
+        assert abs(Jg - Jo) <= 1e-4 * abs(Jo), (raw_c.shape, C, Jg, Jo)
+        assert np.max(np.abs(gg - go)) / np.max(np.abs(go)) <= GRAD_TOL, (raw_c.shape, C, gg, go)
