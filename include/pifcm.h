@@ -149,7 +149,9 @@ pifcm_status pifcm_fcm_init(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm
  * NULL, iters_out [B][P] or NULL.
  * mode PIFCM_SWARM_BATCHED runs the whole swarm as one fused launch per
  * iteration, captured in a HIP graph; PIFCM_SWARM_PLAIN launches one kernel
- * per (b, p) per iteration.  Both give bit-identical results.
+ * per (b, p) per iteration.  Both give bit-identical results under the same
+ * tile shape (pifcm_tune may choose another shape, which changes the order
+ * of the floating-point sums).
  * B <= 32, 1 <= P, B * P <= 65536. */
 #define PIFCM_SWARM_BATCHED 0
 #define PIFCM_SWARM_PLAIN 1
@@ -161,8 +163,10 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
 /* Gradient of J_K = J(U^K, c^K) -- eq (1) after exactly K IFCM iterations
  * from (centres0 (host [C]), U0 (device [N][C])), U0 held constant -- with
  * respect to lambda, xi and the initial centres, by a hand-written adjoint
- * of the K unrolled iterations.  Memberships are kept every ckpt_every
- * iterations (1 <= ckpt_every <= K) and recomputed segment by segment.
+ * of the K unrolled iterations (1 <= K <= 100000).  Memberships are kept
+ * every ckpt_every iterations (1 <= ckpt_every <= K) and recomputed segment
+ * by segment; the context's workspace grows to about
+ * (K / ckpt_every + ckpt_every + 6) * N * C * 4 bytes.
  * Outputs (host): J_out, dJ_dlambda, dJ_dxi, dJ_dcentres [C].
  * Built for the 3x3x3 neighbourhood (V = 1 without PIFCM_SHELL_SQDIST);
  * PIFCM_E_UNSUPPORTED otherwise. */
