@@ -45,6 +45,7 @@ struct VolDev {
   int32_t tiles1d;     // ceil(active voxels / voxels per block) (pointwise kernels)
   int32_t zbeg, zend;  // planes iterated; the others are fixed context
   int32_t pad;
+  const float* rinv;   // [nz][ny][nx][4] per-ring g_inv and q_inv (two-ring kernel only)
 };
 
 // One (volume, particle) run of a launch.

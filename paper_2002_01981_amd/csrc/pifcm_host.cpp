@@ -53,7 +53,7 @@ struct pifcm_ctx {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::string err;
   int num_cu = 256;
-  DevBuf invg, ubuf, partials, states, jhist, tvol, tpair, flags;
+  DevBuf invg, rinv, ubuf, partials, states, jhist, tvol, tpair, flags;
   DevBuf adj_ck, adj_seg, adj_bar, adj_pq, adj_misc, adj_rs;  // ifcm_backward workspace
   DevBuf tune_u0, tune_state;                          // pifcm_tune workspace
   DevBuf ring_tab;                                     // general-neighbourhood offsets
@@ -217,11 +217,13 @@ TileShape shape_for(pifcm_ctx* ctx, int C, bool m2, const pifcm_volume& v) {
 
 // Launch descriptor of a volume whose planes [zbeg, zend) are iterated
 // (zend < 0: all planes).
-VolDev make_vol(const pifcm_volume& v, const float* invg, TileShape ts, int zbeg = 0, int zend = -1) {
+VolDev make_vol(const pifcm_volume& v, const float* invg, TileShape ts, int zbeg = 0, int zend = -1,
+                const float* rinv = nullptr) {
   if (zend < 0) zend = v.nz;
   VolDev d{};
   d.x = v.x;
   d.invg = invg;
+  d.rinv = rinv;
   d.nx = v.nx;
   d.ny = v.ny;
   d.nz = v.nz;
@@ -254,7 +256,8 @@ int grid_for(pifcm_ctx* ctx, int nitems, int occupancy, int per_group = 1) {
 // Set up invariants of `nv` volumes into ctx->invg (concatenated) and check
 // intensities; optionally check rows of caller U0 pointers.
 pifcm_status prepare_volumes(pifcm_ctx* ctx, const pifcm_volume* vols, int nv, int C,
-                             const float* const* U0s, std::vector<size_t>& invg_off) {
+                             const float* const* U0s, std::vector<size_t>& invg_off,
+                             const pifcm_params* ring2 = nullptr) {
   size_t total = 0;
   invg_off.resize(nv);
   for (int b = 0; b < nv; ++b) {
@@ -262,6 +265,15 @@ pifcm_status prepare_volumes(pifcm_ctx* ctx, const pifcm_volume* vols, int nv, i
     total += (nvox(vols[b]) + 63) / 64 * 64;
   }
   TRY(ensure(ctx, ctx->invg, total * sizeof(float), "iteration invariants"));
+  if (ring2) {
+    // Per-ring invariants of the fused two-ring kernel (4 floats per voxel,
+    // at 4 x the offsets of g_inv).
+    TRY(ensure(ctx, ctx->rinv, total * 4 * sizeof(float), "ring invariants"));
+    for (int b = 0; b < nv; ++b)
+      HIPCHK(launch_ring2_invariants(vols[b].x, (float*)ctx->rinv.p + 4 * invg_off[b], vols[b].nx,
+                                     vols[b].ny, vols[b].nz, (ring2->flags & PIFCM_Q2_SQDIST) ? 1 : 0,
+                                     ctx->s));
+  }
   TRY(ensure(ctx, ctx->flags, 64, "flags"));
   int* flags = (int*)ctx->flags.p;
   HIPCHK(hipMemsetAsync(flags, 0, 64, ctx->s));
@@ -299,27 +311,36 @@ SolveState init_state(const float* c0, int C, float lam, float xi, const pifcm_p
 }
 
 // Which step kernel a launch uses.
-enum Kind { kGather = 0, kFcm = 1, kRing = 2 };
+enum Kind { kGather = 0, kFcm = 1, kRing = 2, kRing2 = 3 };
 
 bool ring_params(const pifcm_params* p) { return p->V > 1 || (p->flags & PIFCM_SHELL_SQDIST); }
+// The two Chebyshev rings of the 5x5x5 cube with C <= 4 run the fused
+// two-ring kernel; other general neighbourhoods walk the offset table.
+bool ring2_params(const pifcm_params* p) {
+  return p->V == 2 && !(p->flags & PIFCM_SHELL_SQDIST) && p->C <= 4;
+}
+bool is_ring(int kind) { return kind == kRing || kind == kRing2; }
 
 // lambda = xi = 0 makes the attraction factor of eq (4) exactly 1 for every
 // neighbourhood: plain FCM.
 int kind_of(const pifcm_params* p, bool zero_weights) {
   if (zero_weights) return kFcm;
-  return ring_params(p) ? kRing : kGather;
+  return ring_params(p) ? (ring2_params(p) ? kRing2 : kRing) : kGather;
 }
 
 int occupancy_of(int kind, int C, int nw, bool m2, bool step) {
   if (kind == kFcm) return fcm_occupancy(C, m2, step);
   if (kind == kRing) return ring_occupancy(C, m2, step);
+  if (kind == kRing2) return ring2_occupancy(C, m2, step);
   return gather_occupancy(C, nw, m2, step);
 }
 
 // Work items in flight per work group.
 // Work items a work group takes at a time: one per wave for the tiled
 // kernels, one for the pointwise kernels.
-int items_per_group(int kind, int nw) { return kind == kGather ? nw : kind == kRing ? kRingWaves : 1; }
+int items_per_group(int kind, int nw) {
+  return kind == kGather ? nw : kind == kRing ? kRingWaves : kind == kRing2 ? kRing2Waves : 1;
+}
 
 // Offsets of the general neighbourhood (eq (9) up to the reach of V), sorted
 // by ring (Chebyshev shell, or squared distance with PIFCM_SHELL_SQDIST) with
@@ -374,9 +395,10 @@ pifcm_status prepare_ring(pifcm_ctx* ctx, const pifcm_params* p) {
 // per-pair finalise that adds the tile sums and advances the state.
 hipError_t launch_step(int C, const LaunchArgs& a, int grid, int nw, bool m2, int kind, bool step,
                        hipStream_t s) {
-  hipError_t e = kind == kFcm    ? launch_fcm(C, a, grid, m2, step, s)
-                 : kind == kRing ? launch_ring(C, a, grid, m2, step, s)
-                                 : launch_gather(C, a, grid, nw, m2, step, s);
+  hipError_t e = kind == kFcm     ? launch_fcm(C, a, grid, m2, step, s)
+                 : kind == kRing  ? launch_ring(C, a, grid, m2, step, s)
+                 : kind == kRing2 ? launch_ring2(C, a, grid, m2, step, s)
+                                  : launch_gather(C, a, grid, nw, m2, step, s);
   if (e != hipSuccess) return e;
   return launch_finalize(C, a, a.nvol * a.P, step, s);
 }
@@ -393,7 +415,7 @@ LaunchArgs make_args(const pifcm_ctx* ctx, const VolDev* vols_dev, const PairDev
   a.q2_sqdist = (p->flags & PIFCM_Q2_SQDIST) ? 1 : 0;
   a.m = p->m;
   a.use_1d = kind == kFcm ? 1 : 0;  // the pointwise kernel's 1D tiles
-  if (kind == kRing) {
+  if (is_ring(kind)) {
     a.ring = (const RingOff*)ctx->ring_tab.p;
     a.nring = ctx->ring_n;
     a.pad1 = ctx->ring_gen;  // part of the graph cache key
@@ -454,7 +476,7 @@ void pifcm_destroy(pifcm_ctx* ctx) {
   if (ctx->s) (void)hipStreamSynchronize(ctx->s);
   if (ctx->graph.exec) (void)hipGraphExecDestroy(ctx->graph.exec);
   if (ctx->graph.graph) (void)hipGraphDestroy(ctx->graph.graph);
-  for (DevBuf* b : {&ctx->invg, &ctx->ubuf, &ctx->partials, &ctx->states, &ctx->jhist, &ctx->tvol,
+  for (DevBuf* b : {&ctx->invg, &ctx->rinv, &ctx->ubuf, &ctx->partials, &ctx->states, &ctx->jhist, &ctx->tvol,
                     &ctx->tpair, &ctx->flags, &ctx->adj_ck, &ctx->adj_seg, &ctx->adj_bar,
                     &ctx->adj_pq, &ctx->adj_misc, &ctx->adj_rs, &ctx->tune_u0, &ctx->tune_state, &ctx->ring_tab,
                     &ctx->conf, &ctx->pso_state})
@@ -501,7 +523,7 @@ pifcm_status pifcm_workspace_bytes(pifcm_ctx* ctx, int64_t* device_bytes, int64_
   if (!ctx) return PIFCM_E_INVALID;
   ctx->err.clear();
   int64_t d = 0;
-  for (const DevBuf* b : {&ctx->invg, &ctx->ubuf, &ctx->partials, &ctx->states, &ctx->jhist,
+  for (const DevBuf* b : {&ctx->invg, &ctx->rinv, &ctx->ubuf, &ctx->partials, &ctx->states, &ctx->jhist,
                           &ctx->tvol, &ctx->tpair, &ctx->flags, &ctx->adj_ck, &ctx->adj_seg,
                           &ctx->adj_bar, &ctx->adj_pq, &ctx->adj_misc, &ctx->adj_rs, &ctx->tune_u0,
                           &ctx->tune_state, &ctx->ring_tab, &ctx->conf, &ctx->pso_state})
@@ -575,12 +597,13 @@ pifcm_status solve_impl(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_par
   const bool m2 = p->m == 2.0f;
   const int kind = kind_of(p, lambda == 0.0f && xi == 0.0f);
   const size_t N = nvox(*vol);
-  if (kind == kRing) TRY(prepare_ring(ctx, p));
+  if (is_ring(kind)) TRY(prepare_ring(ctx, p));
   std::vector<size_t> off;
   const float* u0s[1] = {U_in};
-  TRY(prepare_volumes(ctx, vol, 1, C, u0s, off));
+  TRY(prepare_volumes(ctx, vol, 1, C, u0s, off, kind == kRing2 ? p : nullptr));
   const TileShape ts = shape_for(ctx, C, m2, *vol);
-  std::vector<VolDev> vh{make_vol(*vol, (const float*)ctx->invg.p, ts, zbeg, zend)};
+  std::vector<VolDev> vh{make_vol(*vol, (const float*)ctx->invg.p, ts, zbeg, zend,
+                                  kind == kRing2 ? (const float*)ctx->rinv.p : nullptr)};
   const int slots = std::max(vh[0].tiles, vh[0].tiles1d);
   TRY(ensure(ctx, ctx->ubuf, N * C * sizeof(float), "memberships"));
   TRY(ensure(ctx, ctx->partials, (size_t)slots * (2 * C + 1) * sizeof(float), "tile sums"));
@@ -766,8 +789,12 @@ pifcm_status swarm_core(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
   const int C = p->C;
   const bool m2 = p->m == 2.0f;
   TRY(begin(ctx));
+  // lambda = xi = 0 for every particle: plain FCM kernels.
+  bool zero = true;
+  for (long k = 0; k < 2L * B * P; ++k) zero = zero && particles[k] == 0.0f;
+  const int kind = kind_of(p, zero);
   std::vector<size_t> off;
-  TRY(prepare_volumes(ctx, vols, B, C, U0_check, off));
+  TRY(prepare_volumes(ctx, vols, B, C, U0_check, off, kind == kRing2 ? p : nullptr));
 
   // Tile shape: one per launch (the batched kernel has one TY).
   const TileShape ts0 = shape_for(ctx, C, m2, vols[0]);
@@ -789,7 +816,10 @@ pifcm_status swarm_core(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
   TRY(ensure(ctx, ctx->states, npairs * sizeof(SolveState), "solve states"));
   const size_t pin_bytes = npairs * (sizeof(SolveState) + sizeof(PairDev)) + sizeof(VolDev) * B + 4096;
   TRY(ensure_pinned(ctx, pin_bytes));
-  for (int b = 0; b < B; ++b) vh[b].invg = (const float*)ctx->invg.p + off[b];
+  for (int b = 0; b < B; ++b) {
+    vh[b].invg = (const float*)ctx->invg.p + off[b];
+    vh[b].rinv = kind == kRing2 ? (const float*)ctx->rinv.p + 4 * off[b] : nullptr;
+  }
 
   char* pin = (char*)ctx->pinned;
   SolveState* hs = (SolveState*)pin;
@@ -816,11 +846,7 @@ pifcm_status swarm_core(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
   HIPCHK(hipMemcpyAsync(ctx->tpair.p, hp, npairs * sizeof(PairDev), hipMemcpyHostToDevice, ctx->s));
   HIPCHK(hipMemcpyAsync(ctx->tvol.p, hv, B * sizeof(VolDev), hipMemcpyHostToDevice, ctx->s));
 
-  // lambda = xi = 0 for every particle: plain FCM kernels.
-  bool zero = true;
-  for (long k = 0; k < 2L * B * P; ++k) zero = zero && particles[k] == 0.0f;
-  const int kind = kind_of(p, zero);
-  if (kind == kRing) TRY(prepare_ring(ctx, p));
+  if (is_ring(kind)) TRY(prepare_ring(ctx, p));
   const VolDev* vdev = (const VolDev*)ctx->tvol.p;
   const PairDev* pdev = (const PairDev*)ctx->tpair.p;
   const int occ = occupancy_of(kind, C, ts0.nw, m2, true);
@@ -1000,7 +1026,7 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
   const bool m2 = p->m == 2.0f;
   const int kind = kind_of(p, lambda == 0.0f && xi == 0.0f);
   const size_t N = nvox(*vol);
-  if (kind == kRing) TRY(prepare_ring(ctx, p));
+  if (is_ring(kind)) TRY(prepare_ring(ctx, p));
   const size_t UB = N * C * sizeof(float);
   TRY(begin(ctx));
   std::vector<size_t> off;

@@ -16,8 +16,16 @@ hipError_t launch_gather(int C, const LaunchArgs& a, int grid, int ty, bool m2, 
 hipError_t launch_finalize(int C, const LaunchArgs& a, int npairs, bool step, hipStream_t s);
 // Pointwise FCM step / objective (lambda = xi = 0).
 hipError_t launch_fcm(int C, const LaunchArgs& a, int grid, bool m2, bool step, hipStream_t s);
-// Waves (one tile each) per work group of the general-neighbourhood kernel.
+// Waves (one tile each) per work group of the general-neighbourhood kernel
+// and of the fused two-ring kernel.
 constexpr int kRingWaves = 4;
+constexpr int kRing2Waves = 4;
+// Fused step for the two Chebyshev rings of the 5x5x5 cube, C <= 4 (reads
+// VolDev::rinv, the invariants of launch_ring2_invariants).
+hipError_t launch_ring2(int C, const LaunchArgs& a, int grid, bool m2, bool step, hipStream_t s);
+int ring2_occupancy(int C, bool m2, bool step);
+hipError_t launch_ring2_invariants(const float* x, float* rinv, int nx, int ny, int nz, int q2_sqdist,
+                                   hipStream_t s);
 // IFCM step / objective for general neighbourhoods (a.ring, a.W).
 hipError_t launch_ring(int C, const LaunchArgs& a, int grid, bool m2, bool step, hipStream_t s);
 int ring_occupancy(int C, bool m2, bool step);
