@@ -104,9 +104,9 @@ def adjoint_leg(Context, Params):
 
 
 def ring_leg(Context, Params, vol_raw, dims):
-    """The general-neighbourhood kernel (two Chebyshev rings, 5x5x5, h = 1)
-    on the largest volume of the batch: 8 particles x 5 iterations, batched,
-    timed by the library's HIP events."""
+    """The general neighbourhood of two Chebyshev rings (5x5x5, h = 1; the
+    fused two-ring kernel) on the largest volume of the batch: 8 particles x
+    5 iterations, batched, timed by the library's HIP events."""
     import numpy as np
     import torch
     import synth
@@ -127,7 +127,7 @@ def ring_leg(Context, Params, vol_raw, dims):
     n = int(np.prod(dims))
     per_launch = n * P * (8 * 4 + 4)
     avg = ms / max(launches, 1)
-    return dict(kernel="k_ifcm_ring<4, m=2, step>", neighbourhood="5x5x5, 2 rings, h=1",
+    return dict(kernel="k_ifcm_ring2<4, m=2, step>", neighbourhood="5x5x5, 2 rings, h=1",
                 volume_zyx=list(dims), particles=P, iterations=T, avg_launch_us=round(avg * 1e3, 2),
                 value=n * 4 * P / (avg * 1e-3), unit="voxel-cluster-iters/s",
                 algorithmic_GBps=round(per_launch / (avg * 1e-3) / 1e9, 1))
