@@ -80,6 +80,15 @@ def test_rings_other_c_and_m(ctx, C, m):
     _run(ctx, raw, C, 2, 1.0, 0, 0.3, 0.3, 3, m=m)
 
 
+def test_two_rings_tiles_split_along_z(ctx):
+    """A volume deeper than one tile (45 planes against 32 per tile): the
+    planes at a tile's ends take their two planes of context from the
+    neighbouring tile's planes."""
+    raw, _ = synth.random_ellipsoids(shape=(45, 9, 21), seed=102, sigma=0.07)
+    _run(ctx, raw, 4, 2, 1.0, 0, 0.35, 0.3, 3)
+    _run(ctx, raw, 3, 2, 0.7, Q2, 0.5, 0.2, 2)
+
+
 def test_rings_flat_and_tiny_volumes(ctx):
     raw = np.zeros((4, 6, 7), np.float32)
     raw[:, :, 4:] = 1.0
