@@ -89,6 +89,14 @@ def test_two_rings_tiles_split_along_z(ctx):
     _run(ctx, raw, 3, 2, 0.7, Q2, 0.5, 0.2, 2)
 
 
+def test_two_rings_volumes_smaller_than_a_tile(ctx):
+    """The fused two-ring kernel on a line, a 2 x 3 x 2 block and a single
+    plane: most of each ring lies outside the volume."""
+    for shape, C, seed in (((1, 1, 5), 2, 103), ((2, 3, 2), 3, 104), ((1, 6, 9), 4, 105)):
+        raw = synth.random_ellipsoids(shape=shape, seed=seed, sigma=0.07)[0]
+        _run(ctx, raw, C, 2, 1.0, 0, 0.45, 0.3, 3)
+
+
 def test_rings_flat_and_tiny_volumes(ctx):
     raw = np.zeros((4, 6, 7), np.float32)
     raw[:, :, 4:] = 1.0
