@@ -231,16 +231,27 @@ def main():
     per_launch_bytes = sum(nvox) * P * (8 * C + 4)
     avg_launch_ms = kern_ms / max(launches, 1)
     achieved = per_launch_bytes / (avg_launch_ms * 1e-3) / 1e9
-    traffic = None
+    traffic = valu = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
         if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == "ragged6-swarm64":
             traffic = tr.get("hbm_bytes_per_launch")
+            # VALU issue of the same kernel: rocprofv3 SQ_INSTS_VALU per launch
+            # against 1024 SIMDs issuing one wave64 instruction per 4 cycles at
+            # the engine clock the card holds under this benchmark.
+            if tr.get("valu_instructions_per_launch") and tr.get("sclk_mhz_under_bench"):
+                n = tr["valu_instructions_per_launch"]
+                issue_ms = n / (1024 * tr["sclk_mhz_under_bench"] * 1e6 / 4) * 1e3
+                valu = dict(instructions_per_launch=n,
+                            per_voxel=round(n * 64 / (sum(nvox) * P), 1),
+                            sclk_mhz=tr["sclk_mhz_under_bench"], issue_ms=round(issue_ms, 3),
+                            issue_fraction=round(issue_ms / avg_launch_ms, 3))
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=traffic,
                     kernel=KERNEL, avg_launch_us=round(avg_launch_ms * 1e3, 2),
-                    launches=int(launches), algorithmic_bytes_per_launch=per_launch_bytes)
+                    launches=int(launches), algorithmic_bytes_per_launch=per_launch_bytes,
+                    valu_issue=valu)
 
     plain = None
     if not args.no_plain and mode == PIFCM_SWARM_BATCHED:
