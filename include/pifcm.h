@@ -166,7 +166,7 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
  * of the K unrolled iterations (1 <= K <= 100000).  Memberships are kept
  * every ckpt_every iterations (1 <= ckpt_every <= K) and recomputed segment
  * by segment; the context's workspace grows to about
- * (K / ckpt_every + ckpt_every + 6) * N * C * 4 bytes.
+ * (K / ckpt_every + ckpt_every + 5) * N * C * 4 bytes.
  * Outputs (host): J_out, dJ_dlambda, dJ_dxi, dJ_dcentres [C].
  * Built for the 3x3x3 neighbourhood (V = 1 without PIFCM_SHELL_SQDIST);
  * PIFCM_E_UNSUPPORTED otherwise. */

@@ -42,6 +42,20 @@ constexpr int kAdjZc = 64;                   // planes per tile
 // leave room for in LDS.
 constexpr int kAdjPW = 4;                    // waves per work group of k_adj_point
 
+// Inverse of the denominator of eq (7) for voxel (gx, gy, gz): the weights of
+// its in-volume neighbours summed from its position (in-plane edges weigh 1,
+// in-plane corners wCa; per existing off-plane the centre 1, edges wEb,
+// corners wCb).  Both adjoint kernels form it with this one function, so the
+// transpose rebuilds Q bit for bit.
+__device__ __forceinline__ float adj_qinv(int gx, int gy, int gz, int nx, int ny, int nz, float wCa,
+                                          float wEb, float wCb) {
+  const int ex = (gx > 0) + (gx < nx - 1), ey = (gy > 0) + (gy < ny - 1);
+  const float e = (float)(ex + ey), co = (float)(ex * ey);
+  const float q0 = e + wCa * co, q1 = 1.f + wEb * e + wCb * co;
+  const int np = (gz > 0) + (gz < nz - 1);
+  return np == 2 ? 1.f / (q0 + 2.f * q1) : (np == 1 ? 1.f / (q0 + q1) : (q0 > 0.f ? 1.f / q0 : 0.f));
+}
+
 // The per-voxel part of the adjoint of one iteration on wave-private
 // z-streaming tiles (the layout of the fused forward step): each plane of a
 // tile plus its halo is staged once in the wave's LDS as (x, U) per cell,
@@ -50,8 +64,8 @@ constexpr int kAdjPW = 4;                    // waves per work group of k_adj_po
 // the weights of eq (7) depend only on the class), and a voxel whose three
 // planes are done is finalised: it recomputes the forward values of eqs (4),
 // (2) from (U^t, c^t) and applies the adjoint formulas above, writing its
-// transpose sources (P, Q) and adding its dJ/dc, dJ/dlambda, dJ/dxi terms to
-// the lane's sums.  Each wave leaves its sums in its own slot.
+// transpose source da (the transpose forms P and Q from it) and adding its
+// dJ/dc, dJ/dlambda, dJ/dxi terms to the lane's sums.  Each wave leaves its sums in its own slot.
 template <int C, bool M2, bool EVAL>
 __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
   constexpr int CP = (C + 3) / 4 * 4;
@@ -115,17 +129,6 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
     const size_t halo_xy = hvalid ? (size_t)hy * nx + hx : 0;
     float* const sc = &s_c[wave][0][0];
 
-    // Denominator of eq (7) from the column position and the number of
-    // existing off-planes (0, 1, 2).
-    float invQ0, invQ1, invQ2;
-    {
-      const int ex = (gx > 0) + (gx < nx - 1), ey = (gy > 0) + (gy < ny - 1);
-      const float e = (float)(ex + ey), co = (float)(ex * ey);
-      const float q0 = e + wCa * co, q1 = 1.f + wEb * e + wCb * co;
-      invQ0 = q0 > 0.f ? 1.f / q0 : 0.f;
-      invQ1 = 1.f / (q0 + q1);
-      invQ2 = 1.f / (q0 + 2.f * q1);
-    }
 
     // Prefetch registers of one plane: own cell (x, g_inv, U) and halo cell.
     float rx, rg, ru[C], hxv, hu[C];
@@ -179,7 +182,7 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
       const float* own = cell_at(bz, 0, 0);
       const float xv = own[0];
       const float gi = fabsf(gs[S]);
-      const float iq = (z > 0 && z < nz - 1) ? invQ2 : ((z > 0 || z < nz - 1) ? invQ1 : invQ0);
+      const float iq = adj_qinv(gx, gy, z, nx, ny, nz, wCa, wEb, wCb);
       float H[C], F[C], av[C], dd[C], e[C], d[C];
 #pragma unroll
       for (int j = 0; j < C; ++j) {
@@ -247,19 +250,19 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
           dbar[j] = -dw * w[j] / ((m - 1.f) * d[j]);
         }
       }
-      float pq[2 * C];
+      // da is the transpose's source: P = -lambda da g_inv, Q = -xi da q_inv
+      // are rebuilt there from the voxel's g_inv and position.
+      float da[C];
       const float keep = active ? 1.f : 0.f;
 #pragma unroll
       for (int j = 0; j < C; ++j) {
         const float de = e[j] > kDFloor ? dbar[j] * keep : 0.f;
-        const float da = de * dd[j] * dd[j];
+        da[j] = de * dd[j] * dd[j];
         acc[j] += -2.f * de * av[j] * dd[j];  // dJ/dc_j
-        acc[C] += -da * H[j];                // dJ/dlambda
-        acc[C + 1] += -da * F[j];            // dJ/dxi
-        pq[j] = -a.lam * da * gi;
-        pq[C + j] = -a.xi * da * iq;
+        acc[C] += -da[j] * H[j];             // dJ/dlambda
+        acc[C + 1] += -da[j] * F[j];         // dJ/dxi
       }
-      if (active) store_row<2 * C>(as_global(a.PQ) + i * (2 * C), pq);
+      if (active) store_row<C>(as_global(a.PQ) + i * C, da);
     };
 
     auto plane = [&](int p, int SA, int SB, int SC) __attribute__((always_inline)) {
@@ -363,7 +366,8 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
 // fused forward step): a wave owns 16 x 4 columns of a tile of zc planes,
 // each plane of the tile plus a one-voxel halo is staged once in the wave's
 // LDS as (xc, P, Q) per cell -- xc the cell's intensity as the cell uses it
-// in eq (5) (shifted by -1 for a flat neighbourhood) -- and every lane adds
+// in eq (5) (shifted by -1 for a flat neighbourhood), P and Q formed from the
+// cell's da, g_inv and position -- and every lane adds
 // its 3 x 3 in-plane cells to the three voxels of its column they touch.
 // For the Q part the in-plane cells are summed per offset class first (the
 // weights of eq (7) depend only on the class).
@@ -412,50 +416,53 @@ __global__ __launch_bounds__(64 * adj_waves<C>()) void k_adj_transpose_tiled(con
     const bool hvalid = hlane && hx >= 0 && hx < nx && hy >= 0 && hy < ny;
     const size_t own_xy = active ? (size_t)gy * nx + gx : 0;
     const size_t halo_xy = hvalid ? (size_t)hy * nx + hx : 0;
-    // eq (7) denominators do not enter here (they are folded into Q); the
-    // class weights do.
     float* const sc = &s_c[wave][0][0];
 
-    // Prefetch registers of one plane: own and halo cell.
-    float rxc, rx, rp[2 * C], hxc, hp[2 * C];
+    // Prefetch registers of one plane: own and halo cell (intensity as the
+    // cell uses it in eq (5), its |g_inv| and q_inv, and da).
+    float rxc, rx, rgi, rqi, rd[C], hxc, hgi, hqi, hd[C];
     auto load_plane = [&](int q) __attribute__((always_inline)) {
       const bool pv = q >= 0 && q < nz;
+      rx = rxc = rgi = rqi = hxc = hgi = hqi = 0.f;
+#pragma unroll
+      for (int j = 0; j < C; ++j) rd[j] = hd[j] = 0.f;
       if (pv && active) {
         const size_t i = (size_t)q * psz + own_xy;
         rx = a.x[i];
-        rxc = a.invg[i] < 0.f ? rx - 1.f : rx;
-        load_row<2 * C>(as_global(a.PQ) + i * (2 * C), rp);
-      } else {
-        rx = rxc = 0.f;
-#pragma unroll
-        for (int j = 0; j < 2 * C; ++j) rp[j] = 0.f;
+        const float g = a.invg[i];
+        rxc = g < 0.f ? rx - 1.f : rx;
+        rgi = fabsf(g);
+        rqi = adj_qinv(gx, gy, q, nx, ny, nz, wCa, wEb, wCb);
+        load_row<C>(as_global(a.PQ) + i * C, rd);
       }
       if (pv && hvalid) {
         const size_t i = (size_t)q * psz + halo_xy;
         const float xh = a.x[i];
-        hxc = a.invg[i] < 0.f ? xh - 1.f : xh;
-        load_row<2 * C>(as_global(a.PQ) + i * (2 * C), hp);
-      } else {
-        hxc = 0.f;
-#pragma unroll
-        for (int j = 0; j < 2 * C; ++j) hp[j] = 0.f;
+        const float g = a.invg[i];
+        hxc = g < 0.f ? xh - 1.f : xh;
+        hgi = fabsf(g);
+        hqi = adj_qinv(hx, hy, q, nx, ny, nz, wCa, wEb, wCb);
+        load_row<C>(as_global(a.PQ) + i * C, hd);
       }
     };
-    auto store_cell = [&](float* cell, float xc, const float (&pq)[2 * C]) __attribute__((always_inline)) {
+    // P = -lambda da g_inv and Q = -xi da q_inv of the cell (the products the
+    // per-voxel kernel would have formed).
+    auto store_cell = [&](float* cell, float xc, float gi, float qi, const float (&dav)[C])
+        __attribute__((always_inline)) {
       cell[0] = xc;
       float P[C], Q[C];
 #pragma unroll
       for (int j = 0; j < C; ++j) {
-        P[j] = pq[j];
-        Q[j] = pq[C + j];
+        P[j] = -a.lam * dav[j] * gi;
+        Q[j] = -a.xi * dav[j] * qi;
       }
       lds_cell_store<C, CP>(cell + 4, P);  // offset 4 keeps the float4s aligned
       lds_cell_store<C, CP>(cell + 4 + CP, Q);
     };
     auto store_plane = [&](int buf) __attribute__((always_inline)) {
       float* base = sc + buf * kAdjCells * CW;
-      store_cell(base + own_cell * CW, rxc, rp);
-      if (hlane) store_cell(base + halo_cell * CW, hxc, hp);
+      store_cell(base + own_cell * CW, rxc, rgi, rqi, rd);
+      if (hlane) store_cell(base + halo_cell * CW, hxc, hgi, hqi, hd);
     };
 
     // Target slots (voxels p-1, p, p+1 of the lane's column): P-part and

@@ -1045,7 +1045,7 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
   TRY(ensure(ctx, ctx->adj_ck, (size_t)std::max(nck, 1) * UB, "checkpoints"));
   TRY(ensure(ctx, ctx->adj_seg, (size_t)std::max(S - 1, 1) * UB, "segment states"));
   TRY(ensure(ctx, ctx->adj_bar, 2 * UB, "adjoint memberships"));
-  TRY(ensure(ctx, ctx->adj_pq, 2 * UB, "transpose sources"));
+  TRY(ensure(ctx, ctx->adj_pq, UB, "transpose sources"));
   TRY(ensure(ctx, ctx->adj_misc, adj_slots * sizeof(float) + hist_doubles * sizeof(double) +
                                      (size_t)(K + 1) * C * sizeof(float) + 1024, "adjoint sums"));
   TRY(ensure(ctx, ctx->partials, (size_t)slots * (2 * C + 1) * sizeof(float), "tile sums"));

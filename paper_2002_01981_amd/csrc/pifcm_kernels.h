@@ -58,7 +58,7 @@ struct AdjArgs {
   const double* cbar_next; // dJ/dc^(t+1) [C]            (iteration pass)
   const float* c_next;     // c^(t+1) [C]                (iteration pass)
   const double* B_next;    // eq (3) denominators of c^(t+1) [C]
-  float* PQ;               // [N][2C] transpose sources
+  float* PQ;               // [N][C] da, the transpose source (P and Q are formed from it)
   float* Ubar_direct;      // [N][C] direct term of the objective-only pass
   float* partials;         // [adjoint_slots][C + 2] per-wave sums
   int32_t num_cu;          // compute units of the device (grid sizing)
