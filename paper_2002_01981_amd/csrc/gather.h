@@ -55,12 +55,8 @@ constexpr int kHX = kWX + 2, kHY = kWY + 2;    // staged plane with halo
 constexpr int kNCell = kHX * kHY;              // 108 cells
 constexpr int kNHalo = kNCell - 64;            // 44 halo cells, one per lane
 
-#ifndef PIFCM_GATHER_ATTR
-#define PIFCM_GATHER_ATTR
-#endif
-
 template <int C, bool M2, int NW, bool STEP>
-__global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const LaunchArgs a) {
+__global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
   constexpr int CP = (C + 3) / 4 * 4;
   constexpr int CH = C - 1;  // clusters whose H is gathered
   constexpr int NV = STEP ? 2 * C + 1 : 1;
@@ -278,9 +274,6 @@ __global__ __launch_bounds__(64 * NW) PIFCM_GATHER_ATTR void k_ifcm_gather(const
       const bool doB = !GEN || (p >= zlo && p < zhi);
       const bool doC = !GEN || p + 1 < zhi;
       __builtin_amdgcn_wave_barrier();
-#ifdef PIFCM_PLANE_SCHED_FENCE
-      __builtin_amdgcn_sched_barrier(0);
-#endif
       // Centre values for g (shifted by -1 for a flat neighbourhood).
       const float xA = doA ? sx_at(bprev, 0, 0) : 0.f;
       const float xcA = gs[SA] < 0.f ? xA - 1.f : xA;
