@@ -45,6 +45,26 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def copy_bandwidth(torch, mib=1024, reps=5):
+    """GB/s of a plain device-to-device copy (read + write) of mib MiB: the
+    bandwidth a streaming kernel reaches on this card, beside the peak."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(vol_raw, seconds):
     """The FP64 oracle, as it stands, on one (volume, particle) pair of the
     workload: IFCM steps at (lambda, xi) = (0.3, 0.4) on this host's cores
@@ -247,10 +267,17 @@ def main():
                             per_voxel=round(n * 64 / (sum(nvox) * P), 1),
                             sclk_mhz=tr["sclk_mhz_under_bench"], issue_ms=round(issue_ms, 3),
                             issue_fraction=round(issue_ms / avg_launch_ms, 3))
+    copy_gbps = copy_bandwidth(torch)
+    log(f"plain device copy: {copy_gbps:.1f} GB/s")
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=traffic,
                     kernel=KERNEL, avg_launch_us=round(avg_launch_ms * 1e3, 2),
                     launches=int(launches), algorithmic_bytes_per_launch=per_launch_bytes,
+                    # measured HBM bytes (counters) over the live launch time,
+                    # and what a plain 1 GiB copy reaches in the same run
+                    hbm_GBps_measured=(round(traffic / (avg_launch_ms * 1e-3) / 1e9, 1)
+                                       if traffic else None),
+                    plain_copy_GBps=round(copy_gbps, 1),
                     valu_issue=valu)
 
     plain = None

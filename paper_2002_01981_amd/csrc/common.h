@@ -41,6 +41,37 @@ typedef float f2v __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ float frcp(float v) { return __builtin_amdgcn_rcpf(v); }
 
+// A pointer that is the same in every lane, pinned to scalar registers (a
+// select of descriptor fields can otherwise leave it in vector registers, to
+// be read back before every memory instruction that uses it as a base).
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
+// A uniform base the optimiser may not re-associate with a lane offset: kept
+// in scalar registers, so base + 32-bit lane offset stays one memory
+// instruction with no vector address arithmetic.
+template <typename T>
+__device__ __forceinline__ T* opaque_base(T* p) {
+  asm("" : "+s"(p));
+  return p;
+}
+// base + a lane offset held in a variable that is redefined (in place, no
+// code) at each use: its widening then stays next to the access instead of
+// being hoisted out of the loop as a 64-bit vector address.
+__device__ __forceinline__ const gfloat* at_lane(const gfloat* base, uint32_t& off) {
+  asm("" : "+v"(off));
+  return at_byte(base, off);
+}
+__device__ __forceinline__ gfloat* at_lane(gfloat* base, uint32_t& off) {
+  asm("" : "+v"(off));
+  return at_byte(base, off);
+}
+
 __device__ __forceinline__ int vol_of_item(const LaunchArgs& a, int it) {
   int b = 0;
   while (b + 1 < a.nvol && it >= a.item_begin[b + 1]) ++b;
@@ -135,11 +166,13 @@ __device__ __forceinline__ float pow_m(float u, float m) {
   else return u > 0.f ? exp2f(m * log2f(u)) : 0.f;
 }
 
-// Memberships of eq (2) from squared distances d2[0..C), d2 > 0.
+// Memberships of eq (2) from squared distances d2[0..C), d2 > 0, times
+// scale (1, or 0 to zero a row).
 // m == 2: u_j = (1/d2_j) / sum_k (1/d2_k).  Otherwise u_j is proportional to
 // (d2_min / d2_j)^(1/(m-1)), which is eq (2) scaled so no term overflows.
 template <int C, bool M2>
-__device__ __forceinline__ void memberships(const float (&d2)[C], float m, float (&u)[C]) {
+__device__ __forceinline__ void memberships(const float (&d2)[C], float m, float (&u)[C],
+                                            float scale = 1.f) {
   if constexpr (M2 && C <= 4) {
     // u_j = P_j / sum_k P_k with P_j the product of the other d2: one
     // reciprocal.  d2 lies in [1e-12, 2e3] (|lambda|, |xi| <= 1e3), so the
@@ -162,7 +195,7 @@ __device__ __forceinline__ void memberships(const float (&d2)[C], float m, float
     float s = 0.f;
 #pragma unroll
     for (int j = 0; j < C; ++j) s += P[j];
-    const float r = frcp(s);
+    const float r = frcp(s) * scale;
 #pragma unroll
     for (int j = 0; j < C; ++j) u[j] = P[j] * r;
   } else if constexpr (M2) {
@@ -172,7 +205,7 @@ __device__ __forceinline__ void memberships(const float (&d2)[C], float m, float
       u[j] = frcp(d2[j]);
       s += u[j];
     }
-    const float r = frcp(s);
+    const float r = frcp(s) * scale;
 #pragma unroll
     for (int j = 0; j < C; ++j) u[j] *= r;
   } else {
@@ -187,7 +220,7 @@ __device__ __forceinline__ void memberships(const float (&d2)[C], float m, float
       u[j] = exp2f((lmin - log2f(d2[j])) * e);
       s += u[j];
     }
-    const float r = 1.f / s;
+    const float r = scale / s;
 #pragma unroll
     for (int j = 0; j < C; ++j) u[j] *= r;
   }

@@ -103,8 +103,8 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
     const SolveState* st = pr.st;
     if (STEP && ld_const(&st->stop)) continue;
     const int t = STEP ? ld_const(&st->iter) + 1 : ld_const(&st->iter);
-    const float* Uin = STEP ? u_in_of(pr, t) : u_state_of(pr, t);
-    float* Uout = STEP ? u_out_of(pr, t) : nullptr;
+    const float* Uin = uniform_ptr(STEP ? u_in_of(pr, t) : u_state_of(pr, t));
+    float* Uout = STEP ? uniform_ptr(u_out_of(pr, t)) : nullptr;
     float cj[C];
 #pragma unroll
     for (int j = 0; j < C; ++j) cj[j] = ld_const(&st->c[(STEP ? t - 1 : t) & 1][j]);
@@ -119,6 +119,7 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
     const int zlo = vd.zbeg + tzi * vd.zc, zhi = min(zlo + vd.zc, vd.zend);
     const int gx = x0 + tx, gy = y0 + ty;
     const bool active = gx < nx && gy < ny;
+    const float amask = active ? 1.f : 0.f;
     const int hx = x0 - 1 + hcx, hy = y0 - 1 + hcy;
     const bool hvalid = hlane && hx >= 0 && hx < nx && hy >= 0 && hy < ny;
     // 32-bit offsets from the first staged plane of the tile (the host keeps
@@ -129,8 +130,11 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
     const gfloat* Gb = as_global(vd.invg) + (size_t)zb * psz;
     const gfloat* Ub = as_global(Uin) + (size_t)zb * psz * C;
     gfloat* Ob = STEP ? as_global(Uout) + (size_t)zb * psz * C : nullptr;
-    const uint32_t own_xy = active ? (uint32_t)gy * nx + gx : 0u;
-    const uint32_t halo_xy = hvalid ? (uint32_t)hy * nx + hx : 0u;
+    // Lane byte offsets within a plane of x / g_inv (4 B per voxel); U rows
+    // are C times that.  Per plane, the base moves in scalar registers.
+    uint32_t own_ofs = active ? ((uint32_t)gy * nx + gx) * 4u : 0u;
+    uint32_t halo_ofs = hvalid ? ((uint32_t)hy * nx + hx) * 4u : 0u;
+    uint32_t own_ofs_u = own_ofs * C, halo_ofs_u = halo_ofs * C;
 
     // Denominator of eq (7): in-plane edges e and corners e_x * e_y, plus for
     // each of the az existing off-planes a centre, e edges and e_x * e_y
@@ -159,52 +163,77 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
       lds_cell_load<C, CP>(suw + (buf * kNCell + dy * kHX + dx) * CP, u);
     };
 
-    // Prefetch registers of the next plane.
+    // Prefetch registers of the next plane.  A lane whose column lies outside
+    // the volume (in x or y) does so for the whole tile: the tile's first
+    // planes (full form) stage zeros for its cells in all three buffers, and
+    // the interior planes (LIGHT form) neither load nor store them.
     float rx, rg, ru[C], rhx, rhu[C];
-    auto load_plane = [&](int q) __attribute__((always_inline)) {
+    auto zero_prefetch = [&]() __attribute__((always_inline)) {
+      rx = 0.f;
+      rg = 1.f;
+      rhx = 0.f;
+#pragma unroll
+      for (int j = 0; j < C; ++j) ru[j] = rhu[j] = 0.f;
+    };
+    auto load_plane = [&](int q, auto LIGHTc) __attribute__((always_inline)) {
+      constexpr bool LIGHT = decltype(LIGHTc)::value;
       const bool pv = q >= 0 && q < nz;
-      const uint32_t pofs = (uint32_t)(q - zb) * psz;
+      const uint32_t pb = (uint32_t)(q - zb) * psz * 4u;
+      const gfloat* Xq = opaque_base(at_byte(Xb, pb));
+      const gfloat* Gq = opaque_base(at_byte(Gb, pb));
+      const gfloat* Uq = opaque_base(at_byte(Ub, pb * C));
+      if constexpr (LIGHT) {
+        if (!pv) {
+          zero_prefetch();
+          return;
+        }
+      }
       if (pv && active) {
-        const uint32_t ob = (pofs + own_xy) * 4u;
-        rx = *at_byte(Xb, ob);
-        rg = *at_byte(Gb, ob);
-        load_row<C>(at_byte(Ub, ob * C), ru);
-      } else {
+        rx = *at_lane(Xq, own_ofs);
+        rg = *at_lane(Gq, own_ofs);
+        load_row<C>(at_lane(Uq, own_ofs_u), ru);
+      } else if (!LIGHT) {
         rx = 0.f;
         rg = 1.f;
 #pragma unroll
         for (int j = 0; j < C; ++j) ru[j] = 0.f;
       }
       if (pv && hvalid) {
-        const uint32_t ob = (pofs + halo_xy) * 4u;
-        rhx = *at_byte(Xb, ob);
-        load_row<C>(at_byte(Ub, ob * C), rhu);
-      } else {
+        rhx = *at_lane(Xq, halo_ofs);
+        load_row<C>(at_lane(Uq, halo_ofs_u), rhu);
+      } else if (!LIGHT) {
         rhx = 0.f;
 #pragma unroll
         for (int j = 0; j < C; ++j) rhu[j] = 0.f;
       }
     };
-    auto store_plane = [&](int buf) __attribute__((always_inline)) {
+    auto store_plane = [&](int buf, auto LIGHTc) __attribute__((always_inline)) {
+      constexpr bool LIGHT = decltype(LIGHTc)::value;
       float* sx = &s_x[wave][buf][0];
       float* su = &s_u[wave][buf][0];
-      sx[own_cell] = rx;
-      lds_cell_store<C, CP>(su + own_cell * CP, ru);
-      if (hlane) {
+      // The light form skips the cells of lanes outside the volume: they
+      // hold the zeros the full form staged.
+      if (!LIGHT || active) {
+        sx[own_cell] = rx;
+        lds_cell_store<C, CP>(su + own_cell * CP, ru);
+      }
+      if (LIGHT ? hvalid : hlane) {
         sx[halo_cell] = rhx;
         lds_cell_store<C, CP>(su + halo_cell * CP, rhu);
       }
     };
 
     // Slots of the three voxels in flight: gathered H numerators, F class
-    // sums and the stored g_inv (its sign marks a flat neighbourhood).
-    float hn[3][CH], fn[3][C], gs[3];
+    // sums, the stored g_inv (its sign marks a flat neighbourhood) and the
+    // centre value that forms g (shifted by -1 for a flat neighbourhood).
+    float hn[3][CH], fn[3][C], gs[3], xs[3];
     float acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.f;
 #pragma unroll
     for (int s2 = 0; s2 < 3; ++s2) {
       gs[s2] = 1.f;
+      xs[s2] = 0.f;
 #pragma unroll
       for (int j = 0; j < CH; ++j) hn[s2][j] = 0.f;
 #pragma unroll
@@ -225,9 +254,9 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
       const float g = fabsf(gs[S]);
       // a_j = 1 - lambda H_j - xi F_j with H_j = hn_j * g, F_j = fn_j * iq.
       const float lg = -lam * g, xq = -xi * iq;
-      float sh = 0.f;
+      float sh = hn[S][0];
 #pragma unroll
-      for (int j = 0; j < CH; ++j) sh += hn[S][j];
+      for (int j = 1; j < CH; ++j) sh += hn[S][j];
       // Last cluster by sum_j H_ij = 1 (0 when the voxel has no neighbour).
       const float hlast = g != 0.f ? fmaf(-g, sh, 1.f) : 0.f;
       float d2[C];
@@ -241,13 +270,17 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
         Jv = fmaf(pow_m<M2>(uo[j], a.m), d2[j], Jv);  // eq (1)
       }
       if constexpr (STEP) {
+        // eq (2); a lane outside the volume gets zeros (scale 0), so its
+        // terms vanish from the sums of eq (3) with no masking.
         float un[C];
-        memberships<C, M2>(d2, a.m, un);  // eq (2)
-        const uint32_t ob = ((uint32_t)(z - zb) * psz + own_xy) * (4u * C);
-        if (active) store_row<C>(at_byte(Ob, ob), un);
+        memberships<C, M2>(d2, a.m, un, amask);
+        if (active) {
+          gfloat* Oz = opaque_base(at_byte(Ob, (uint32_t)(z - zb) * psz * (4u * C)));
+          store_row<C>(at_lane(Oz, own_ofs_u), un);
+        }
 #pragma unroll
         for (int j = 0; j < C; ++j) {
-          const float w = active ? pow_m<M2>(un[j], a.m) : 0.f;
+          const float w = pow_m<M2>(un[j], a.m);
           acc[j] = fmaf(w, xv, acc[j]);  // eq (3) numerator
           acc[C + j] += w;                // eq (3) denominator
         }
@@ -274,10 +307,10 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
       const bool doB = !GEN || (p >= zlo && p < zhi);
       const bool doC = !GEN || p + 1 < zhi;
       __builtin_amdgcn_wave_barrier();
-      // Centre values for g (shifted by -1 for a flat neighbourhood).
-      const float xA = doA ? sx_at(bprev, 0, 0) : 0.f;
-      const float xcA = gs[SA] < 0.f ? xA - 1.f : xA;
-      const float xC = rg < 0.f ? rx - 1.f : rx;  // voxel p+1, prefetched
+      // Centre values for g: voxels p-1 and p from their slots, p+1 from the
+      // prefetch registers.
+      const float xcA = xs[SA];
+      const float xC = rg < 0.f ? rx - 1.f : rx;
       if (pv) {
         float E[C], Co[C], Pc[C];
         // H gathers accumulate straight into the slots of voxels p-1 and p.
@@ -288,8 +321,7 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
         for (int j = 0; j < CH; ++j) hC[j] = 0.f;
         float (&hA)[CH] = hn[SA];
         float (&hB)[CH] = hn[SB];
-        const float xB = sx_at(bp, 0, 0);
-        const float xcB = gs[SB] < 0.f ? xB - 1.f : xB;
+        const float xcB = xs[SB];
 #pragma unroll
         for (int dy = -1; dy <= 1; ++dy) {
 #pragma unroll
@@ -362,9 +394,10 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
       // staging (and its wait for the prefetch) after this plane's gathers.
       __builtin_amdgcn_sched_barrier(0);
       if (!GEN || p + 1 <= zhi) {
-        store_plane(bnext);
+        store_plane(bnext, std::integral_constant<bool, !GEN>{});
         gs[SC] = rg;
-        if (!GEN || p + 2 <= zhi) load_plane(p + 2);
+        xs[SC] = xC;
+        if (!GEN || p + 2 <= zhi) load_plane(p + 2, std::integral_constant<bool, !GEN>{});
       }
       if (doA) finalize(p - 1, SAc, bprev);
       // Keep the next plane's gathers after this plane's store.
@@ -377,6 +410,7 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
 #pragma unroll
       for (int s2 = 0; s2 < 2; ++s2) {
         gs[s2] = gs[s2 + 1];
+        xs[s2] = xs[s2 + 1];
 #pragma unroll
         for (int j = 0; j < CH; ++j) hn[s2][j] = hn[s2 + 1][j];
 #pragma unroll
@@ -390,12 +424,13 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
     using Bdyn = std::integral_constant<int, -1>;
     using Gen = std::integral_constant<bool, true>;
     using Steady = std::integral_constant<bool, false>;
+    using Full = std::integral_constant<bool, false>;  // staging forms
 
     // Prologue: stage plane zlo-1 (zeros outside the volume) in buffer 0,
     // prefetch zlo.
-    load_plane(zlo - 1);
-    store_plane(0);
-    load_plane(zlo);
+    load_plane(zlo - 1, Full{});
+    store_plane(0, Full{});
+    load_plane(zlo, Full{});
     // The tile's first two planes, the interior in groups of three, the
     // rest.  Three loops rather than one, so the interior loop's back edge
     // carries the slots in the registers they entered with (no copies).
