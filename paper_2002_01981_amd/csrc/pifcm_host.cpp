@@ -186,13 +186,18 @@ pifcm_status check_params(pifcm_ctx* ctx, const pifcm_params* p) {
   return PIFCM_OK;
 }
 
-pifcm_status check_volume(pifcm_ctx* ctx, const pifcm_volume* v) {
+// (C: the cluster count of the call, from validated params.)
+pifcm_status check_volume(pifcm_ctx* ctx, const pifcm_volume* v, int C) {
   if (!v) return fail(ctx, PIFCM_E_INVALID, "volume is NULL");
   if (!v->x) return fail(ctx, PIFCM_E_INVALID, "volume intensities are NULL");
   if (v->nx < 1 || v->ny < 1 || v->nz < 1)
     return fail(ctx, PIFCM_E_INVALID, "volume dims %d x %d x %d must be >= 1", v->nx, v->ny, v->nz);
   const double n = (double)v->nx * v->ny * v->nz;
   if (n > 4.0e9) return fail(ctx, PIFCM_E_INVALID, "volume of %.0f voxels is too large", n);
+  // The kernels address the planes of a tile with 32-bit byte offsets: three
+  // planes of memberships must stay below 2^31 bytes.
+  if (3.0 * v->nx * v->ny * C * 4.0 >= 2147483648.0)
+    return fail(ctx, PIFCM_E_INVALID, "planes of %d x %d voxels are too large for C = %d", v->nx, v->ny, C);
   return PIFCM_OK;
 }
 
@@ -680,8 +685,8 @@ pifcm_status solve_impl(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_par
 pifcm_status check_solve_args(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
                               float lambda, float xi, const float* centres_in, const float* U_in,
                               const float* U_out) {
-  TRY(check_volume(ctx, vol));
   TRY(check_params(ctx, p));
+  TRY(check_volume(ctx, vol, p->C));
   if (!(std::fabs(lambda) <= kMaxWeight) || !(std::fabs(xi) <= kMaxWeight))
     return fail(ctx, PIFCM_E_INVALID, "lambda and xi must be finite with magnitude <= %g", kMaxWeight);
   if (!centres_in) return fail(ctx, PIFCM_E_INVALID, "centres_in is NULL");
@@ -983,7 +988,7 @@ pifcm_status swarm_evaluate(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
     return fail(ctx, PIFCM_E_INVALID, "particles, centres0, U0 and fitness_out must be non-NULL");
   const int C = p->C;
   for (int b = 0; b < B; ++b) {
-    TRY(check_volume(ctx, &vols[b]));
+    TRY(check_volume(ctx, &vols[b], C));
     if (!U0[b] || !aligned16(U0[b])) return fail(ctx, PIFCM_E_INVALID, "U0[%d] is NULL or not 16-byte aligned", b);
     for (int j = 0; j < C; ++j)
       if (!std::isfinite(centres0[b * C + j])) return fail(ctx, PIFCM_E_INVALID, "centres0[%d][%d] is not finite", b, j);
@@ -1008,8 +1013,8 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
                            double* dJ_dxi, double* dJ_dcentres) {
   if (!ctx) return PIFCM_E_INVALID;
   ctx->err.clear();
-  TRY(check_volume(ctx, vol));
   TRY(check_params(ctx, p));
+  TRY(check_volume(ctx, vol, p->C));
   if (ring_params(p))
     return fail(ctx, PIFCM_E_UNSUPPORTED, "the adjoint is built for the 3x3x3 neighbourhood (V = 1)");
   if (!(std::fabs(lambda) <= kMaxWeight) || !(std::fabs(xi) <= kMaxWeight))
@@ -1224,8 +1229,8 @@ pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
     }
     return PIFCM_OK;
   }
-  for (int b = 0; b < B; ++b) TRY(check_volume(ctx, &vols[b]));
   const int C = p->C;
+  for (int b = 0; b < B; ++b) TRY(check_volume(ctx, &vols[b], C));
   const bool m2 = p->m == 2.0f;
   // Initial memberships: eq (2) with the attraction factor 1 for evenly
   // spaced centres, one buffer per volume.
@@ -1468,7 +1473,7 @@ pifcm_status pifcm_pso_interleaved(pifcm_ctx* ctx, const pifcm_volume* vols, int
   if (!centres0 || !U0) return fail(ctx, PIFCM_E_INVALID, "centres0 and U0 must be non-NULL");
   const int C = p->C;
   for (int b = 0; b < B; ++b) {
-    TRY(check_volume(ctx, &vols[b]));
+    TRY(check_volume(ctx, &vols[b], C));
     if (!U0[b] || !aligned16(U0[b])) return fail(ctx, PIFCM_E_INVALID, "U0[%d] is NULL or not 16-byte aligned", b);
     if (U_best_out && (!U_best_out[b] || !aligned16(U_best_out[b])))
       return fail(ctx, PIFCM_E_INVALID, "U_best_out[%d] is NULL or not 16-byte aligned", b);

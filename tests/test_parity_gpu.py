@@ -283,6 +283,11 @@ def test_error_paths(ctx):
     assert status(lambda: ctx.ifcm_solve(x, _P(), 0.3, 0.3, c0, U_in=Uok, U_out=Uok)) == PIFCM_E_INVALID
     big = torch.empty(x.numel() * 4 + 1, device="cuda")
     assert status(lambda: ctx.ifcm_solve(x, _P(), 0.3, 0.3, c0, U_out=big[1:])) == PIFCM_E_INVALID
+    # planes whose three-plane tile would pass 2^31 bytes of U are refused
+    # (the outputs are allocated at full size: nothing is written either way)
+    wide = torch.zeros((1, 8192, 8192), device="cuda")
+    assert status(lambda: ctx.ifcm_solve(wide, _P(), 0.3, 0.3, c0)) == PIFCM_E_INVALID
+    del wide
     # the context still works after errors
     g = ctx.ifcm_solve(x, _P(max_iter=2, eps=0.0), 0.3, 0.3, c0)
     assert g["iters"] == 2 and np.isfinite(g["J"])
