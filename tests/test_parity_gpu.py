@@ -287,7 +287,11 @@ def test_error_paths(ctx):
     # (the outputs are allocated at full size: nothing is written either way)
     wide = torch.zeros((1, 8192, 8192), device="cuda")
     assert status(lambda: ctx.ifcm_solve(wide, _P(), 0.3, 0.3, c0)) == PIFCM_E_INVALID
-    del wide
+    Uw = torch.full((wide.numel(), 4), 0.25, device="cuda")
+    assert status(lambda: ctx.swarm_evaluate([wide], _P(), np.array([[0.3, 0.3]]), c0[None],
+                                             [Uw])) == PIFCM_E_INVALID
+    assert status(lambda: ctx.ifcm_backward(wide, _P(), 0.3, 0.3, c0, Uw, 2, 1)) == PIFCM_E_INVALID
+    del wide, Uw
     # the context still works after errors
     g = ctx.ifcm_solve(x, _P(max_iter=2, eps=0.0), 0.3, 0.3, c0)
     assert g["iters"] == 2 and np.isfinite(g["J"])
