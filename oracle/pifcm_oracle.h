@@ -29,8 +29,14 @@
  *                          closed form of a two-voxel volume, uniform-U
  *                          identity, convex-combination bounds of H and F,
  *                          sum-to-one of eq (2), the m = 2 identity
+ *   oracle_init_memberships textbook FCM memberships of the centres
  *   oracle_solve ......... FCM descent, constant image, axis flips,
- *                          transposes and centre permutations
+ *                          transposes and centre permutations; the stop
+ *                          rule against the first small relative change
+ *                          found by hand in a fixed-count run's J list; the
+ *                          fitness against J of the last input state of a
+ *                          run one iteration longer (and textbook FCM's J
+ *                          at lambda = xi = 0)
  *   oracle_solve_slab .... whole-volume slab equals oracle_solve; one-step
  *                          brute force of the active planes; fixed context
  *   oracle_fcm_init ...... sorted centres; equals solve-then-sort

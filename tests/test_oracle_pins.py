@@ -466,3 +466,92 @@ def test_slab_matches_bruteforce_with_fixed_context(orc, zbeg, zend):
     keep = np.ones(x.shape, bool)
     keep[zbeg:zend] = False
     np.testing.assert_array_equal(o["U"][keep.reshape(-1)], U0[keep.reshape(-1)])
+
+
+# ------------------------------------------------- loop control, fitness, U^(0)
+def _nested_case(orc):
+    import synth
+    raw, _ = synth.nested_ellipsoids()
+    return orc.normalize(raw), np.array([0.125, 0.375, 0.625, 0.875])
+
+
+def _first_stop(Jh, eps, cap):
+    """First iteration t >= 2 after which |J(t-1) - J(t-2)| <= eps |J(t-2)|,
+    J(s) being the objective of state s; cap if none."""
+    for t in range(2, cap + 1):
+        if abs(Jh[t - 1] - Jh[t - 2]) <= eps * abs(Jh[t - 2]):
+            return t
+    return cap
+
+
+@pytest.mark.parametrize("lam,xi", [(0.0, 0.0), (0.3, 0.2)])
+def test_stop_rule_is_the_first_small_relative_change(orc, lam, xi):
+    """Section 4 and Algorithm 2 end the iteration once the objective stops
+    changing (reading R12: relative change of J, tested from t = 2).  A run
+    with eps = 0 lists J of every state; for each eps the stopping iteration
+    T is found from that list by hand, and the eps run must stop exactly
+    there, returning the state of a plain T-iteration run bit for bit."""
+    x, c0 = _nested_case(orc)
+    cap = 40
+    ref = orc.solve(x, c0, orc.Params(C=4, m=2.0, eps=0.0, max_iter=cap), lam, xi, want_hist=True)
+    Jh = ref["J_hist"]
+    assert len(Jh) == cap
+    rel = sorted({abs(Jh[t - 1] - Jh[t - 2]) / abs(Jh[t - 2]) for t in range(2, cap + 1)})
+    # eps = 0 means "run max_iter"; a converged FCM run may repeat J exactly
+    rel = [r for r in rel if r > 0]
+    # thresholds strictly between consecutive relative changes (no ties),
+    # above the largest one (T = 2) and below the smallest positive one
+    cuts = [rel[-1] * 2.0, rel[0] * 0.5]
+    cuts += [math.sqrt(a * b) for a, b in zip(rel[:-1], rel[1:]) if a > 0 and b > a * (1 + 1e-6)]
+    seen = set()
+    for eps in cuts[:12]:
+        T = _first_stop(Jh, eps, cap)
+        seen.add(T)
+        o = orc.solve(x, c0, orc.Params(C=4, m=2.0, eps=eps, max_iter=cap), lam, xi,
+                      want_hist=True)
+        assert o["iters"] == T, (eps, o["iters"], T)
+        np.testing.assert_array_equal(o["J_hist"], Jh[:T])
+        f = orc.solve(x, c0, orc.Params(C=4, m=2.0, eps=0.0, max_iter=T), lam, xi)
+        assert np.array_equal(o["U"], f["U"]) and np.array_equal(o["c"], f["c"])
+        assert o["J"] == f["J"]
+    assert 2 in seen and len(seen) >= 3
+
+
+@pytest.mark.parametrize("lam,xi", [(0.0, 0.0), (0.35, 0.25)])
+def test_fitness_is_the_objective_of_the_final_state(orc, lam, xi):
+    """Algorithm 1 step 4 ranks particles by J_m of eq (1), of the state the
+    run ends in (reading R9).  A run of T iterations reports J(U^(T), c^(T)),
+    which a run of T + 1 iterations lists as the objective of its last input
+    state.  With no iteration the fitness is J of the initial state."""
+    x, c0 = _nested_case(orc)
+    for T in (0, 1, 2, 5):
+        a = orc.solve(x, c0, orc.Params(C=4, m=2.0, eps=0.0, max_iter=T), lam, xi)
+        b = orc.solve(x, c0, orc.Params(C=4, m=2.0, eps=0.0, max_iter=T + 1), lam, xi,
+                      want_hist=True)
+        assert a["iters"] == T
+        assert a["J"] == b["J_hist"][T], (T, a["J"], b["J_hist"][T])
+        if lam == 0.0 and xi == 0.0:
+            # plain FCM: the objective of the returned (U, c) by the textbook formula
+            _, _, Jt = textbook_fcm_step(x, a["U"], a["c"], 2.0)
+            assert abs(a["J"] - Jt) <= 1e-12 * Jt
+
+
+@pytest.mark.parametrize("m", [2.0, 2.5, 1.7])
+def test_initial_memberships_are_fcm_memberships_of_the_centres(orc, m):
+    """Without a given U^(0) the run starts from eq (2) with the attraction
+    factor 1: the textbook FCM memberships of the initial centres.  A solve
+    with no iteration must hand that state back, and a one-step solve from it
+    must equal the one-step solve given the textbook memberships."""
+    rng = np.random.default_rng(61)
+    x = _rand_vol(rng, (4, 5, 6))
+    c = np.array([0.1, 0.35, 0.6, 0.9])
+    Ut, _, _ = textbook_fcm_step(x, random_memberships(rng, x.size, 4), c, m)
+    p = orc.Params(C=4, m=m, eps=0.0, max_iter=0)
+    np.testing.assert_allclose(orc.init_memberships(x, c, p), Ut, rtol=1e-12, atol=1e-15)
+    z = orc.solve(x, c, p, 0.4, 0.3)
+    np.testing.assert_allclose(z["U"], Ut, rtol=1e-12, atol=1e-15)
+    p1 = orc.Params(C=4, m=m, eps=0.0, max_iter=1)
+    a = orc.solve(x, c, p1, 0.4, 0.3)
+    b = orc.solve(x, c, p1, 0.4, 0.3, U0=Ut)
+    np.testing.assert_allclose(a["U"], b["U"], rtol=1e-11, atol=1e-14)
+    np.testing.assert_allclose(a["c"], b["c"], rtol=1e-11)
