@@ -332,6 +332,7 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
       __builtin_amdgcn_sched_barrier(0);
     };
 
+    // Plane walk replayed by tests/test_plane_walk.py.
     load_plane(zlo - 1);
     store_plane(0);
     load_plane(zlo);
@@ -554,6 +555,7 @@ __global__ __launch_bounds__(64 * adj_waves<C>()) void k_adj_transpose_tiled(con
       __builtin_amdgcn_sched_barrier(0);
     };
 
+    // Plane walk replayed by tests/test_plane_walk.py.
     load_plane(zlo - 1);
     store_plane(0);
     load_plane(zlo);

@@ -434,6 +434,9 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
     // The tile's first two planes, the interior in groups of three, the
     // rest.  Three loops rather than one, so the interior loop's back edge
     // carries the slots in the registers they entered with (no copies).
+    // The interior's last prefetch reads plane p + 4 <= zhi, which is nz
+    // when the tile ends at the volume's last plane: load_plane keeps its
+    // plane-range test.  tests/test_plane_walk.py replays this walk.
     int p = zlo - 1;
     for (; p <= zlo && p <= zhi; ++p) {
       plane(p, I0{}, I1{}, I2{}, Bdyn{}, Gen{});

@@ -401,10 +401,8 @@ __global__ __launch_bounds__(64 * kRing2Waves) void k_ifcm_ring2(const LaunchArg
       plane(p, I0{}, Gen{});
       shift();
     }
-    // Interior planes in groups of five: the slots rotate by name.  A group
-    // reads planes up to p+6 and own values up to p+7; p + 8 <= zhi keeps
-    // them inside the volume.
-    // Interior planes: every test is true (loads still test the plane).
+    // Interior planes: every per-plane test is true (the loads still test
+    // the plane range).  tests/test_plane_walk.py replays this walk.
     for (; p + 4 <= zhi; ++p) {
       plane(p, I0{}, Steady{});
       shift();
