@@ -143,24 +143,77 @@ def _ip(a):
     return a.ctypes.data_as(ct.POINTER(ct.c_int32))
 
 
-def _dev(t, dtype=None):
+def _is_device(t):
+    return t.is_cuda
+
+
+def _dev(t, dtype=None, numel=None, what="tensor"):
+    """A contiguous device tensor of the given dtype and element count.  The
+    C ABI receives bare pointers and cannot know buffer sizes, so every
+    device buffer is checked here before the library is called."""
     import torch
-    if not (isinstance(t, torch.Tensor) and t.is_cuda):
-        raise TypeError("expected a device tensor")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch tensor, got {type(t).__name__}")
     if dtype is not None and t.dtype != dtype:
-        raise TypeError(f"expected {dtype}, got {t.dtype}")
+        raise TypeError(f"{what}: expected {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what}: {t.numel()} elements, expected {numel}")
     if not t.is_contiguous():
-        raise ValueError("expected a contiguous tensor")
+        raise ValueError(f"{what}: expected a contiguous tensor")
+    if not _is_device(t):
+        raise TypeError(f"{what}: expected a device tensor")
     return t
+
+
+def _memberships(u, x, C, what):
+    """Memberships (N, C) float32 of volume x, on x's device."""
+    import torch
+    _dev(u, torch.float32, x.numel() * C, what)
+    if u.device != x.device:
+        raise ValueError(f"{what} is on {u.device}, the volume on {x.device}")
+    return u
+
+
+def _host_vec(a, n, dtype, what):
+    v = np.ascontiguousarray(a, dtype)
+    if v.size != n:
+        raise ValueError(f"{what}: {v.size} values, expected {n}")
+    return v
 
 
 def _volume(x):
     import torch
-    _dev(x, torch.float32)
+    _dev(x, torch.float32, what="volume")
     if x.dim() != 3:
         raise ValueError("volume must be (Z, Y, X)")
     nz, ny, nx = x.shape
     return _Volume(nx, ny, nz, x.data_ptr())
+
+
+def _volumes(xs, U0s, C):
+    """Volume table of a batch and its B initial-membership pointers."""
+    B = len(xs)
+    if B < 1:
+        raise ValueError("need at least one volume")
+    if len(U0s) != B:
+        raise ValueError(f"{len(U0s)} initial memberships for {B} volumes")
+    vols = (_Volume * B)(*[_volume(x) for x in xs])
+    ptrs = (ct.c_void_p * B)(*[_memberships(u, x, C, f"U0s[{b}]").data_ptr()
+                               for b, (x, u) in enumerate(zip(xs, U0s))])
+    return vols, ptrs
+
+
+def _streams(streams):
+    x0 = np.ascontiguousarray(streams["x0"], np.float64)
+    v0 = np.ascontiguousarray(streams["v0"], np.float64)
+    r1 = np.ascontiguousarray(streams["r1"], np.float64)
+    r2 = np.ascontiguousarray(streams["r2"], np.float64)
+    if r1.ndim != 3 or r1.shape[2] != 2:
+        raise ValueError("r1 must be (G, P, 2)")
+    G, P = r1.shape[0], r1.shape[1]
+    if x0.shape != (P, 2) or v0.shape != (P, 2) or r2.shape != (G, P, 2):
+        raise ValueError("stream shapes do not agree")
+    return x0, v0, r1, r2, G, P
 
 
 class Context:
@@ -200,10 +253,10 @@ class Context:
     # ------------------------------------------------------------ entry points
     def pifcm_normalize(self, raw, out=None):
         import torch
-        _dev(raw, torch.float32)
+        _dev(raw, torch.float32, what="raw")
         if out is None:
             out = torch.empty_like(raw)
-        _dev(out, torch.float32)
+        _dev(out, torch.float32, raw.numel(), "out")
         self._check(self.lib.pifcm_normalize(self.h, raw.data_ptr(), raw.numel(), out.data_ptr()))
         return out
 
@@ -221,11 +274,12 @@ class Context:
                    want_hist=False, U_out=None):
         import torch
         vol = _volume(x)
-        c = np.ascontiguousarray(centres, np.float32)
+        c = _host_vec(centres, p.C, np.float32, "centres")
         if U_in is not None:
-            _dev(U_in, torch.float32)
+            _memberships(U_in, x, p.C, "U_in")
         if U_out is None:
             U_out = torch.empty((x.numel(), p.C), dtype=torch.float32, device=x.device)
+        _memberships(U_out, x, p.C, "U_out")
         lab = torch.empty(x.numel(), dtype=torch.uint8, device=x.device) if labels else None
         cout = np.empty(p.C, np.float32)
         J = np.zeros(1, np.float64)
@@ -249,8 +303,8 @@ class Context:
         fixed as context."""
         import torch
         vol = _volume(x)
-        c = np.ascontiguousarray(centres, np.float32)
-        _dev(U_in, torch.float32)
+        c = _host_vec(centres, p.C, np.float32, "centres")
+        _memberships(U_in, x, p.C, "U_in")
         U_out = torch.empty((x.numel(), p.C), dtype=torch.float32, device=x.device)
         lab = torch.empty(x.numel(), dtype=torch.uint8, device=x.device) if labels else None
         cout = np.empty(p.C, np.float32)
@@ -273,13 +327,14 @@ class Context:
         """xs: list of B (Z, Y, X) tensors; particles: (B, P, 2); centres0:
         (B, C); U0s: list of B (N_b, C) tensors."""
         B = len(xs)
-        vols = (_Volume * B)(*[_volume(x) for x in xs])
+        vols, ptrs = _volumes(xs, U0s, p.C)
         part = np.ascontiguousarray(particles, np.float32)
         if part.ndim == 2:
             part = np.ascontiguousarray(np.broadcast_to(part, (B,) + part.shape))
+        if part.ndim != 3 or part.shape[0] != B or part.shape[2] != 2 or part.shape[1] < 1:
+            raise ValueError(f"particles must be (P, 2) or (B={B}, P, 2), got {part.shape}")
         P = part.shape[1]
-        c0 = np.ascontiguousarray(centres0, np.float32).reshape(B, p.C)
-        ptrs = (ct.c_void_p * B)(*[_dev(u).data_ptr() for u in U0s])
+        c0 = _host_vec(centres0, B * p.C, np.float32, "centres0").reshape(B, p.C)
         fit = np.empty((B, P), np.float64)
         cout = np.empty((B, P, p.C), np.float32)
         it = np.empty((B, P), np.int32)
@@ -289,13 +344,14 @@ class Context:
 
     def ifcm_backward(self, x, p: Params, lam, xi, centres0, U0, K, ckpt_every):
         vol = _volume(x)
-        c = np.ascontiguousarray(centres0, np.float32)
+        c = _host_vec(centres0, p.C, np.float32, "centres0")
+        _memberships(U0, x, p.C, "U0")
         J = np.zeros(1)
         dl = np.zeros(1)
         dx = np.zeros(1)
         dc = np.zeros(p.C)
         self._check(self.lib.ifcm_backward(self.h, ct.byref(vol), ct.byref(p.c()), float(lam),
-                                           float(xi), _fp(c), _dev(U0).data_ptr(), int(K),
+                                           float(xi), _fp(c), U0.data_ptr(), int(K),
                                            int(ckpt_every), _dp(J), _dp(dl), _dp(dx), _dp(dc)))
         return dict(J=float(J[0]), dlam=float(dl[0]), dxi=float(dx[0]), dc=dc)
 
@@ -342,16 +398,9 @@ class Context:
         Returns dict(best_pos (B, 2), best_fit (B,), fit_hist (B, G, P),
         pos_hist (B, G, P, 2))."""
         B = len(xs)
-        vols = (_Volume * B)(*[_volume(x) for x in xs])
-        x0 = np.ascontiguousarray(streams["x0"], np.float64)
-        v0 = np.ascontiguousarray(streams["v0"], np.float64)
-        r1 = np.ascontiguousarray(streams["r1"], np.float64)
-        r2 = np.ascontiguousarray(streams["r2"], np.float64)
-        G, P = r1.shape[0], r1.shape[1]
-        if x0.shape != (P, 2) or v0.shape != (P, 2) or r2.shape != (G, P, 2):
-            raise ValueError("stream shapes do not agree")
-        c0 = np.ascontiguousarray(centres0, np.float32).reshape(B, p.C)
-        ptrs = (ct.c_void_p * B)(*[_dev(u).data_ptr() for u in U0s])
+        vols, ptrs = _volumes(xs, U0s, p.C)
+        x0, v0, r1, r2, G, P = _streams(streams)
+        c0 = _host_vec(centres0, B * p.C, np.float32, "centres0").reshape(B, p.C)
         bp = np.empty((B, 2))
         bf = np.empty(B)
         fh = np.empty((B, G, P))
@@ -368,16 +417,9 @@ class Context:
         U_best (list of B device (N_b, C) tensors) and centres_best (B, C)."""
         import torch
         B = len(xs)
-        vols = (_Volume * B)(*[_volume(x) for x in xs])
-        x0 = np.ascontiguousarray(streams["x0"], np.float64)
-        v0 = np.ascontiguousarray(streams["v0"], np.float64)
-        r1 = np.ascontiguousarray(streams["r1"], np.float64)
-        r2 = np.ascontiguousarray(streams["r2"], np.float64)
-        G, P = r1.shape[0], r1.shape[1]
-        if x0.shape != (P, 2) or v0.shape != (P, 2) or r2.shape != (G, P, 2):
-            raise ValueError("stream shapes do not agree")
-        c0 = np.ascontiguousarray(centres0, np.float32).reshape(B, p.C)
-        ptrs = (ct.c_void_p * B)(*[_dev(u).data_ptr() for u in U0s])
+        vols, ptrs = _volumes(xs, U0s, p.C)
+        x0, v0, r1, r2, G, P = _streams(streams)
+        c0 = _host_vec(centres0, B * p.C, np.float32, "centres0").reshape(B, p.C)
         ub = [torch.empty((x.numel(), p.C), dtype=torch.float32, device=x.device) for x in xs]
         uptr = (ct.c_void_p * B)(*[u.data_ptr() for u in ub])
         cb = np.empty((B, p.C), np.float32)
