@@ -176,17 +176,39 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
                            double* dJ_dxi, double* dJ_dcentres);
 
 /* Pick the work decomposition of the fused step for these volumes -- waves
- * per work group and planes per tile -- by timing a short batched swarm
- * evaluation (P particles spread over [0, 1]^2, a few iterations from FCM
- * memberships of evenly spaced centres) for each candidate.  A candidate is
- * eligible only if its fitnesses and centres agree with the default
- * decomposition's to 1e-5 relative (tilings change the order of the sums,
- * nothing else).  The choice is kept in ctx for these (C, m == 2, shape)
- * keys and used by later calls.  best_out (host, may be NULL) receives a
- * short description (best_len bytes).  The general-neighbourhood kernel has
- * a fixed decomposition: for those parameters nothing is timed. */
+ * per work group, planes per tile and, at C = 4 with P >= 2, particles per
+ * work item (1 or 2: two particles of a volume share its intensities and
+ * the |x_i - x_k| of eq (6)) -- by timing a short batched swarm evaluation
+ * (P particles spread over [0, 1]^2, a few iterations from FCM memberships
+ * of evenly spaced centres) for each candidate.  A candidate is eligible
+ * only if its fitnesses and centres agree with the default decomposition's
+ * to 1e-5 relative and its final memberships of the first two particles on
+ * the smallest volume agree element by element to 1e-4 of their largest
+ * value (tilings change the order of the sums, nothing else).  The choice is
+ * kept in ctx for these (C, m == 2, shape) keys and used by later calls.  If
+ * the environment variable PIFCM_TUNE_CACHE names a file, a choice stored
+ * there for the same device architecture, C, m == 2, V, B, P and shape
+ * bucket (total voxels and largest plane count rounded up to powers of two)
+ * is applied without timing, and a new choice is added to the file (a JSON
+ * object, one entry per line).  best_out (host, may be NULL) receives a short
+ * description (best_len bytes).  The general-neighbourhood kernel has a
+ * fixed decomposition: for those parameters nothing is timed. */
 pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
                         const pifcm_params* p, int32_t P, char* best_out, int32_t best_len);
+
+/* Set the work decomposition of the fused step for these volumes by hand
+ * (what pifcm_tune would otherwise choose): waves per work group (1, 2 or 4),
+ * planes per tile (>= 1; clamped to the volume and to the 32-bit offset
+ * range) and particles per work item (1 or 2; used by batched swarm
+ * launches of P >= 2 particles).  Other values than 4 waves and 1 particle
+ * are built for C = 4 only (PIFCM_E_UNSUPPORTED otherwise).  Kept in ctx for
+ * these (C, m == 2, shape) keys, as a tuned choice is.  Results of every
+ * decomposition agree up to the order of floating-point sums; for a given
+ * waves and planes choice the particles per item do not change any result
+ * bit. */
+pifcm_status pifcm_set_decomposition(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
+                                     const pifcm_params* p, int32_t waves_per_group,
+                                     int32_t planes_per_tile, int32_t particles_per_item);
 
 /* Particle swarm search over (lambda, xi) in [0, 1]^2 -- Algorithm 1 steps
  * 3-9 -- on B volumes at once, each volume with its own swarm of P

@@ -111,6 +111,8 @@ def load_library(path=LIB_PATH):
     lib.ifcm_backward.restype = st
     lib.pifcm_tune.argtypes = [vp, P(_Volume), i32, P(_Params), i32, ct.c_char_p, i32]
     lib.pifcm_tune.restype = st
+    lib.pifcm_set_decomposition.argtypes = [vp, P(_Volume), i32, P(_Params), i32, i32, i32]
+    lib.pifcm_set_decomposition.restype = st
     lib.pifcm_pso.argtypes = [vp, P(_Volume), i32, P(_Params), i32, i32, P(f64), P(f64), P(f64),
                               P(f64), f64, f64, f64, P(f32), P(vp), i32, P(f64), P(f64), P(f64),
                               P(f64)]
@@ -383,6 +385,13 @@ class Context:
         n = ct.c_int64()
         self._check(self.lib.pifcm_get_timing(self.h, ct.byref(ms), ct.byref(n), 1 if reset else 0))
         return ms.value, n.value
+
+    def pifcm_set_decomposition(self, xs, p: Params, waves_per_group=4, planes_per_tile=32,
+                                particles_per_item=1):
+        B = len(xs)
+        vols = (_Volume * B)(*[_volume(x) for x in xs])
+        self._check(self.lib.pifcm_set_decomposition(self.h, vols, B, ct.byref(p.c()), int(waves_per_group),
+                                                     int(planes_per_tile), int(particles_per_item)))
 
     def pifcm_tune(self, xs, p: Params, P):
         B = len(xs)

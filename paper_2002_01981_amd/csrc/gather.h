@@ -25,6 +25,14 @@
 // from the tile's first and last ones run a branch-free body unrolled three
 // times so the slot ring rotates by renaming instead of register moves.
 //
+// Particle sharing.  A work item may hold PT particles (two) of the same
+// volume: the intensities, g_inv and every g_ik = |x_i - x_k| depend on the
+// volume only, so they are loaded, staged and formed once and applied to
+// each particle's memberships, which are staged side by side in the wave's
+// LDS.  Each particle keeps its own slots, sums, centres and output.  A
+// particle past the end of the swarm, or one that has stopped, is computed
+// from a duplicate and its stores are skipped.
+//
 // Arithmetic shortcuts that keep the results those of the equations:
 //   * the denominator of eq (5), sum_k |x_i - x_k|, does not change between
 //     iterations: it is precomputed once per volume as its inverse g_inv;
@@ -55,16 +63,17 @@ constexpr int kHX = kWX + 2, kHY = kWY + 2;    // staged plane with halo
 constexpr int kNCell = kHX * kHY;              // 108 cells
 constexpr int kNHalo = kNCell - 64;            // 44 halo cells, one per lane
 
-template <int C, bool M2, int NW, bool STEP>
+template <int C, bool M2, int NW, bool STEP, int PT>
 __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
   constexpr int CP = (C + 3) / 4 * 4;
   constexpr int CH = C - 1;  // clusters whose H is gathered
   constexpr int NV = STEP ? 2 * C + 1 : 1;
 
   // Three plane buffers per wave: the plane being read, the one before it
-  // (own cells of the voxel being finalised), and the one being staged.
+  // (own cells of the voxel being finalised), and the one being staged; the
+  // memberships of the PT particles side by side.
   __shared__ float s_x[NW][3][kNCell];
-  __shared__ __align__(16) float s_u[NW][3][kNCell * CP];
+  __shared__ __align__(16) float s_u[NW][3][PT][kNCell * CP];
 
   const int lane = threadIdx.x & 63;
   // The wave index is uniform across the wave; say so, so that every value
@@ -97,18 +106,35 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
     const int b = vol_of_item(a, it);
     const VolDev vd = ld_const(a.vols + b);
     const int r = it - a.item_begin[b];
-    const int pidx = r / vd.tiles;
-    const int tile = r - pidx * vd.tiles;
-    const PairDev pr = ld_const(a.pairs + b * a.P + pidx);
-    const SolveState* st = pr.st;
-    if (STEP && ld_const(&st->stop)) continue;
-    const int t = STEP ? ld_const(&st->iter) + 1 : ld_const(&st->iter);
-    const float* Uin = uniform_ptr(STEP ? u_in_of(pr, t) : u_state_of(pr, t));
-    float* Uout = STEP ? uniform_ptr(u_out_of(pr, t)) : nullptr;
-    float cj[C];
+    const int grp = r / vd.tiles;
+    const int tile = r - grp * vd.tiles;
+    // The PT particles of the item: a slot past the swarm repeats the last
+    // particle, and it and a particle that has stopped store nothing.
+    PairDev pr[PT];
+    bool live[PT];
+    bool any = false;
 #pragma unroll
-    for (int j = 0; j < C; ++j) cj[j] = ld_const(&st->c[(STEP ? t - 1 : t) & 1][j]);
-    const float lam = ld_const(&st->lam), xi = ld_const(&st->xi);
+    for (int k = 0; k < PT; ++k) {
+      const int q = grp * PT + k;
+      pr[k] = ld_const(a.pairs + b * a.P + min(q, a.P - 1));
+      live[k] = q < a.P && !(STEP && ld_const(&pr[k].st->stop));
+      any = any || live[k];
+    }
+    if (!any) continue;
+    const float* Uin[PT];
+    float* Uout[PT];
+    float cj[PT][C], lam[PT], xi[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      const SolveState* st = pr[k].st;
+      const int t = STEP ? ld_const(&st->iter) + 1 : ld_const(&st->iter);
+      Uin[k] = uniform_ptr(STEP ? u_in_of(pr[k], t) : u_state_of(pr[k], t));
+      Uout[k] = STEP ? uniform_ptr(u_out_of(pr[k], t)) : nullptr;
+#pragma unroll
+      for (int j = 0; j < C; ++j) cj[k][j] = ld_const(&st->c[(STEP ? t - 1 : t) & 1][j]);
+      lam[k] = ld_const(&st->lam);
+      xi[k] = ld_const(&st->xi);
+    }
     const int nx = vd.nx, ny = vd.ny, nz = vd.nz;
 
     const int txi = tile % vd.ntx;
@@ -128,8 +154,13 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
     const int zb = max(zlo - 1, 0);
     const gfloat* Xb = as_global(vd.x) + (size_t)zb * psz;
     const gfloat* Gb = as_global(vd.invg) + (size_t)zb * psz;
-    const gfloat* Ub = as_global(Uin) + (size_t)zb * psz * C;
-    gfloat* Ob = STEP ? as_global(Uout) + (size_t)zb * psz * C : nullptr;
+    const gfloat* Ub[PT];
+    gfloat* Ob[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      Ub[k] = as_global(Uin[k]) + (size_t)zb * psz * C;
+      Ob[k] = STEP ? as_global(Uout[k]) + (size_t)zb * psz * C : nullptr;
+    }
     // Lane byte offsets within a plane of x / g_inv (4 B per voxel); U rows
     // are C times that.  Per plane, the base moves in scalar registers.
     uint32_t own_ofs = active ? ((uint32_t)gy * nx + gx) * 4u : 0u;
@@ -154,26 +185,28 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
     // every access is a compile-time constant, so LDS addresses are one lane
     // base plus immediate offsets.
     float* const sxw = &s_x[wave][0][0] + own_cell;
-    float* const suw = &s_u[wave][0][0] + own_cell * CP;
+    float* const suw = &s_u[wave][0][0][0] + own_cell * CP;
     auto bufof = [&](int q) { return (q - zlo + 1) % 3; };
     auto sx_at = [&](int buf, int dy, int dx) -> float {
       return sxw[buf * kNCell + dy * kHX + dx];
     };
-    auto su_at = [&](int buf, int dy, int dx, float (&u)[C]) {
-      lds_cell_load<C, CP>(suw + (buf * kNCell + dy * kHX + dx) * CP, u);
+    auto su_at = [&](int buf, int k, int dy, int dx, float (&u)[C]) {
+      lds_cell_load<C, CP>(suw + ((buf * PT + k) * kNCell + dy * kHX + dx) * CP, u);
     };
 
     // Prefetch registers of the next plane.  A lane whose column lies outside
     // the volume (in x or y) does so for the whole tile: the tile's first
     // planes (full form) stage zeros for its cells in all three buffers, and
     // the interior planes (LIGHT form) neither load nor store them.
-    float rx, rg, ru[C], rhx, rhu[C];
+    float rx, rg, ru[PT][C], rhx, rhu[PT][C];
     auto zero_prefetch = [&]() __attribute__((always_inline)) {
       rx = 0.f;
       rg = 1.f;
       rhx = 0.f;
 #pragma unroll
-      for (int j = 0; j < C; ++j) ru[j] = rhu[j] = 0.f;
+      for (int k = 0; k < PT; ++k)
+#pragma unroll
+        for (int j = 0; j < C; ++j) ru[k][j] = rhu[k][j] = 0.f;
     };
     auto load_plane = [&](int q, auto LIGHTc) __attribute__((always_inline)) {
       constexpr bool LIGHT = decltype(LIGHTc)::value;
@@ -181,7 +214,6 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
       const uint32_t pb = (uint32_t)(q - zb) * psz * 4u;
       const gfloat* Xq = opaque_base(at_byte(Xb, pb));
       const gfloat* Gq = opaque_base(at_byte(Gb, pb));
-      const gfloat* Uq = opaque_base(at_byte(Ub, pb * C));
       if constexpr (LIGHT) {
         if (!pv) {
           zero_prefetch();
@@ -191,102 +223,125 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
       if (pv && active) {
         rx = *at_lane(Xq, own_ofs);
         rg = *at_lane(Gq, own_ofs);
-        load_row<C>(at_lane(Uq, own_ofs_u), ru);
+#pragma unroll
+        for (int k = 0; k < PT; ++k) {
+          const gfloat* Uq = opaque_base(at_byte(Ub[k], pb * C));
+          load_row<C>(at_lane(Uq, own_ofs_u), ru[k]);
+        }
       } else if (!LIGHT) {
         rx = 0.f;
         rg = 1.f;
 #pragma unroll
-        for (int j = 0; j < C; ++j) ru[j] = 0.f;
+        for (int k = 0; k < PT; ++k)
+#pragma unroll
+          for (int j = 0; j < C; ++j) ru[k][j] = 0.f;
       }
       if (pv && hvalid) {
         rhx = *at_lane(Xq, halo_ofs);
-        load_row<C>(at_lane(Uq, halo_ofs_u), rhu);
+#pragma unroll
+        for (int k = 0; k < PT; ++k) {
+          const gfloat* Uq = opaque_base(at_byte(Ub[k], pb * C));
+          load_row<C>(at_lane(Uq, halo_ofs_u), rhu[k]);
+        }
       } else if (!LIGHT) {
         rhx = 0.f;
 #pragma unroll
-        for (int j = 0; j < C; ++j) rhu[j] = 0.f;
+        for (int k = 0; k < PT; ++k)
+#pragma unroll
+          for (int j = 0; j < C; ++j) rhu[k][j] = 0.f;
       }
     };
     auto store_plane = [&](int buf, auto LIGHTc) __attribute__((always_inline)) {
       constexpr bool LIGHT = decltype(LIGHTc)::value;
       float* sx = &s_x[wave][buf][0];
-      float* su = &s_u[wave][buf][0];
       // The light form skips the cells of lanes outside the volume: they
       // hold the zeros the full form staged.
       if (!LIGHT || active) {
         sx[own_cell] = rx;
-        lds_cell_store<C, CP>(su + own_cell * CP, ru);
+#pragma unroll
+        for (int k = 0; k < PT; ++k) lds_cell_store<C, CP>(&s_u[wave][buf][k][0] + own_cell * CP, ru[k]);
       }
       if (LIGHT ? hvalid : hlane) {
         sx[halo_cell] = rhx;
-        lds_cell_store<C, CP>(su + halo_cell * CP, rhu);
+#pragma unroll
+        for (int k = 0; k < PT; ++k) lds_cell_store<C, CP>(&s_u[wave][buf][k][0] + halo_cell * CP, rhu[k]);
       }
     };
 
     // Slots of the three voxels in flight: gathered H numerators, F class
-    // sums, the stored g_inv (its sign marks a flat neighbourhood) and the
-    // centre value that forms g (shifted by -1 for a flat neighbourhood).
-    float hn[3][CH], fn[3][C], gs[3], xs[3];
-    float acc[NV];
+    // sums (per particle), the stored g_inv (its sign marks a flat
+    // neighbourhood) and the centre value that forms g (shifted by -1 for a
+    // flat neighbourhood).
+    float hn[3][PT][CH], fn[3][PT][C], gs[3], xs[3];
+    float acc[PT][NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = 0.f;
+    for (int k = 0; k < PT; ++k)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[k][v] = 0.f;
 #pragma unroll
     for (int s2 = 0; s2 < 3; ++s2) {
       gs[s2] = 1.f;
       xs[s2] = 0.f;
 #pragma unroll
-      for (int j = 0; j < CH; ++j) hn[s2][j] = 0.f;
+      for (int k = 0; k < PT; ++k) {
 #pragma unroll
-      for (int j = 0; j < C; ++j) fn[s2][j] = 0.f;
+        for (int j = 0; j < CH; ++j) hn[s2][k][j] = 0.f;
+#pragma unroll
+        for (int j = 0; j < C; ++j) fn[s2][k][j] = 0.f;
+      }
     }
 
     // Finalise voxel z of slot S; its own cell is in buffer bz:
-    // eqs (5)/(7) ratios, (4), (1), (2), (3).
+    // eqs (5)/(7) ratios, (4), (1), (2), (3), per particle.
     auto finalize = [&](int z, auto Sc, int bz) __attribute__((always_inline)) {
       constexpr int S = decltype(Sc)::value;
       // Computed by every lane (a lane outside the volume sees staged zeros
       // and finite distances); only its store and its sums are masked, so no
       // conditional block holds the arithmetic.
       const float xv = sx_at(bz, 0, 0);
-      float uo[C];
-      su_at(bz, 0, 0, uo);
       const float iq = (z > 0 && z < nz - 1) ? invQ2 : ((z > 0 || z < nz - 1) ? invQ1 : invQ0);
       const float g = fabsf(gs[S]);
-      // a_j = 1 - lambda H_j - xi F_j with H_j = hn_j * g, F_j = fn_j * iq.
-      const float lg = -lam * g, xq = -xi * iq;
-      float sh = hn[S][0];
 #pragma unroll
-      for (int j = 1; j < CH; ++j) sh += hn[S][j];
-      // Last cluster by sum_j H_ij = 1 (0 when the voxel has no neighbour).
-      const float hlast = g != 0.f ? fmaf(-g, sh, 1.f) : 0.f;
-      float d2[C];
-      float Jv = 0.f;
+      for (int k = 0; k < PT; ++k) {
+        float uo[C];
+        su_at(bz, k, 0, 0, uo);
+        // a_j = 1 - lambda H_j - xi F_j with H_j = hn_j * g, F_j = fn_j * iq.
+        const float lg = -lam[k] * g, xq = -xi[k] * iq;
+        float sh = hn[S][k][0];
 #pragma unroll
-      for (int j = 0; j < C; ++j) {
-        const float ah = j < CH ? fmaf(lg, hn[S][j < CH ? j : 0], 1.f) : fmaf(-lam, hlast, 1.f);
-        const float av = fmaf(xq, fn[S][j], ah);  // eq (4) factor
-        const float dd = xv - cj[j];
-        d2[j] = fmaxf(dd * dd * av, kDFloor);
-        Jv = fmaf(pow_m<M2>(uo[j], a.m), d2[j], Jv);  // eq (1)
-      }
-      if constexpr (STEP) {
-        // eq (2); a lane outside the volume gets zeros (scale 0), so its
-        // terms vanish from the sums of eq (3) with no masking.
-        float un[C];
-        memberships<C, M2>(d2, a.m, un, amask);
-        if (active) {
-          gfloat* Oz = opaque_base(at_byte(Ob, (uint32_t)(z - zb) * psz * (4u * C)));
-          store_row<C>(at_lane(Oz, own_ofs_u), un);
-        }
+        for (int j = 1; j < CH; ++j) sh += hn[S][k][j];
+        // Last cluster by sum_j H_ij = 1 (0 when the voxel has no neighbour).
+        const float hlast = g != 0.f ? fmaf(-g, sh, 1.f) : 0.f;
+        float d2[C];
+        float Jv = 0.f;
 #pragma unroll
         for (int j = 0; j < C; ++j) {
-          const float w = pow_m<M2>(un[j], a.m);
-          acc[j] = fmaf(w, xv, acc[j]);  // eq (3) numerator
-          acc[C + j] += w;                // eq (3) denominator
+          const float ah =
+              j < CH ? fmaf(lg, hn[S][k][j < CH ? j : 0], 1.f) : fmaf(-lam[k], hlast, 1.f);
+          const float av = fmaf(xq, fn[S][k][j], ah);  // eq (4) factor
+          const float dd = xv - cj[k][j];
+          d2[j] = fmaxf(dd * dd * av, kDFloor);
+          Jv = fmaf(pow_m<M2>(uo[j], a.m), d2[j], Jv);  // eq (1)
         }
-        acc[2 * C] += Jv;  // 0 for a lane outside: its staged memberships are 0
-      } else {
-        acc[0] += Jv;
+        if constexpr (STEP) {
+          // eq (2); a lane outside the volume gets zeros (scale 0), so its
+          // terms vanish from the sums of eq (3) with no masking.
+          float un[C];
+          memberships<C, M2>(d2, a.m, un, amask);
+          if (active && live[k]) {
+            gfloat* Oz = opaque_base(at_byte(Ob[k], (uint32_t)(z - zb) * psz * (4u * C)));
+            store_row<C>(at_lane(Oz, own_ofs_u), un);
+          }
+#pragma unroll
+          for (int j = 0; j < C; ++j) {
+            const float w = pow_m<M2>(un[j], a.m);
+            acc[k][j] = fmaf(w, xv, acc[k][j]);  // eq (3) numerator
+            acc[k][C + j] += w;                   // eq (3) denominator
+          }
+          acc[k][2 * C] += Jv;  // 0 for a lane outside: its staged memberships are 0
+        } else {
+          acc[k][0] += Jv;
+        }
       }
     };
 
@@ -312,81 +367,96 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
       const float xcA = xs[SA];
       const float xC = rg < 0.f ? rx - 1.f : rx;
       if (pv) {
-        float E[C], Co[C], Pc[C];
+        float E[PT][C], Co[PT][C], Pc[PT][C];
         // H gathers accumulate straight into the slots of voxels p-1 and p.
-        float hC[CH];
+        float hC[PT][CH];
 #pragma unroll
-        for (int j = 0; j < C; ++j) E[j] = Co[j] = Pc[j] = 0.f;
+        for (int k = 0; k < PT; ++k) {
 #pragma unroll
-        for (int j = 0; j < CH; ++j) hC[j] = 0.f;
-        float (&hA)[CH] = hn[SA];
-        float (&hB)[CH] = hn[SB];
+          for (int j = 0; j < C; ++j) E[k][j] = Co[k][j] = Pc[k][j] = 0.f;
+#pragma unroll
+          for (int j = 0; j < CH; ++j) hC[k][j] = 0.f;
+        }
         const float xcB = xs[SB];
 #pragma unroll
         for (int dy = -1; dy <= 1; ++dy) {
 #pragma unroll
           for (int dx = -1; dx <= 1; ++dx) {
             const float xk = sx_at(bp, dy, dx);
-            float u[C];
-            su_at(bp, dy, dx, u);
             const int n = (dx != 0) + (dy != 0);
+            // eq (6), formed once for all particles
+            const float gA = fabsf(xcA - xk), gB = fabsf(xcB - xk), gC = fabsf(xC - xk);
 #pragma unroll
-            for (int j = 0; j < C; ++j) {
-              if (n == 0) Pc[j] = u[j] * u[j];
-              else if (n == 1) E[j] = fmaf(u[j], u[j], E[j]);
-              else Co[j] = fmaf(u[j], u[j], Co[j]);
-            }
-            if (doA) {
-              const float g = fabsf(xcA - xk);  // eq (6)
+            for (int k = 0; k < PT; ++k) {
+              float u[C];
+              su_at(bp, k, dy, dx, u);
 #pragma unroll
-              for (int j = 0; j < CH; ++j) hA[j] = fmaf(u[j], g, hA[j]);
-            }
-            if (doB && n != 0) {
-              const float g = fabsf(xcB - xk);
+              for (int j = 0; j < C; ++j) {
+                if (n == 0) Pc[k][j] = u[j] * u[j];
+                else if (n == 1) E[k][j] = fmaf(u[j], u[j], E[k][j]);
+                else Co[k][j] = fmaf(u[j], u[j], Co[k][j]);
+              }
+              if (doA) {
 #pragma unroll
-              for (int j = 0; j < CH; ++j) hB[j] = fmaf(u[j], g, hB[j]);
-            }
-            if (doC) {
-              const float g = fabsf(xC - xk);
+                for (int j = 0; j < CH; ++j) hn[SA][k][j] = fmaf(u[j], gA, hn[SA][k][j]);
+              }
+              if (doB && n != 0) {
 #pragma unroll
-              for (int j = 0; j < CH; ++j) hC[j] = fmaf(u[j], g, hC[j]);
+                for (int j = 0; j < CH; ++j) hn[SB][k][j] = fmaf(u[j], gB, hn[SB][k][j]);
+              }
+              if (doC) {
+#pragma unroll
+                for (int j = 0; j < CH; ++j) hC[k][j] = fmaf(u[j], gC, hC[k][j]);
+              }
             }
           }
+          // With two particles, one row of cells at a time: keeps the row's
+          // LDS reads, not the whole window's, in registers.
+          if constexpr (PT > 1) __builtin_amdgcn_sched_barrier(0);
         }
-        float Sa[C], Sb[C];
 #pragma unroll
-        for (int j = 0; j < C; ++j) {
-          Sa[j] = fmaf(wCa, Co[j], wEa * E[j]);
-          Sb[j] = fmaf(wCb, Co[j], fmaf(wEb, E[j], wPb * Pc[j]));
-        }
-        if (doA) {
+        for (int k = 0; k < PT; ++k) {
+          float Sa[C], Sb[C];
 #pragma unroll
-          for (int j = 0; j < C; ++j) fn[SA][j] += Sb[j];
-        }
-        if (doB) {
+          for (int j = 0; j < C; ++j) {
+            Sa[j] = fmaf(wCa, Co[k][j], wEa * E[k][j]);
+            Sb[j] = fmaf(wCb, Co[k][j], fmaf(wEb, E[k][j], wPb * Pc[k][j]));
+          }
+          if (doA) {
 #pragma unroll
-          for (int j = 0; j < C; ++j) fn[SB][j] += Sa[j];
-        }
-        if (doC) {
+            for (int j = 0; j < C; ++j) fn[SA][k][j] += Sb[j];
+          }
+          if (doB) {
 #pragma unroll
-          for (int j = 0; j < CH; ++j) hn[SC][j] = hC[j];
+            for (int j = 0; j < C; ++j) fn[SB][k][j] += Sa[j];
+          }
+          if (doC) {
 #pragma unroll
-          for (int j = 0; j < C; ++j) fn[SC][j] = Sb[j];
+            for (int j = 0; j < CH; ++j) hn[SC][k][j] = hC[k][j];
+#pragma unroll
+            for (int j = 0; j < C; ++j) fn[SC][k][j] = Sb[j];
+          }
         }
         // The gathers are complete here: the compiler may not sink them past
         // the staging below (which waits on the prefetch loads).
 #pragma unroll
         for (int s2 = 0; s2 < 3; ++s2) {
 #pragma unroll
-          for (int j = 0; j < CH; ++j) asm volatile("" : "+v"(hn[s2][j]));
+          for (int k = 0; k < PT; ++k) {
 #pragma unroll
-          for (int j = 0; j < C; ++j) asm volatile("" : "+v"(fn[s2][j]));
+            for (int j = 0; j < CH; ++j) asm volatile("" : "+v"(hn[s2][k][j]));
+#pragma unroll
+            for (int j = 0; j < C; ++j) asm volatile("" : "+v"(fn[s2][k][j]));
+          }
         }
       } else if (doC) {
 #pragma unroll
-        for (int j = 0; j < CH; ++j) hn[SC][j] = 0.f;
+        for (int k = 0; k < PT; ++k) {
 #pragma unroll
-        for (int j = 0; j < C; ++j) fn[SC][j] = 0.f;
+          for (int j = 0; j < CH; ++j) hn[SC][k][j] = 0.f;
+#pragma unroll
+          for (int j = 0; j < C; ++j) fn[SC][k][j] = 0.f;
+        }
       }
       // Stage plane p+1 and prefetch p+2 before finalising p-1: the global
       // store of p-1's memberships then has a whole plane of work to drain
@@ -412,9 +482,12 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
         gs[s2] = gs[s2 + 1];
         xs[s2] = xs[s2 + 1];
 #pragma unroll
-        for (int j = 0; j < CH; ++j) hn[s2][j] = hn[s2 + 1][j];
+        for (int k = 0; k < PT; ++k) {
 #pragma unroll
-        for (int j = 0; j < C; ++j) fn[s2][j] = fn[s2 + 1][j];
+          for (int j = 0; j < CH; ++j) hn[s2][k][j] = hn[s2 + 1][k][j];
+#pragma unroll
+          for (int j = 0; j < C; ++j) fn[s2][k][j] = fn[s2 + 1][k][j];
+        }
       }
     };
 
@@ -454,55 +527,85 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
       shift();
     }
 
-    wave_tile_store<NV>(pr, tile, acc);
+#pragma unroll
+    for (int k = 0; k < PT; ++k)
+      if (live[k]) wave_tile_store<NV>(pr[k], tile, acc[k]);
   }
 }
 
-// Launch / occupancy of one C with NW waves per work group.  NW variants
-// exist only where ALL_NW is set (the C = 4 fast path); elsewhere NW = 4.
-template <int C, bool M2, int NW>
+// Launch / occupancy of one C with NW waves per work group and PT particles
+// per work item.  NW and PT variants exist only where ALL_NW is set (the
+// C = 4 fast path); elsewhere NW = 4 and PT = 1.
+template <int C, bool M2, int NW, int PT>
 static hipError_t launch_gather_ct(const LaunchArgs& a, int grid, bool step, hipStream_t s) {
-  if (step) hipLaunchKernelGGL((k_ifcm_gather<C, M2, NW, true>), dim3(grid), dim3(64 * NW), 0, s, a);
-  else hipLaunchKernelGGL((k_ifcm_gather<C, M2, NW, false>), dim3(grid), dim3(64 * NW), 0, s, a);
+  if (step) hipLaunchKernelGGL((k_ifcm_gather<C, M2, NW, true, PT>), dim3(grid), dim3(64 * NW), 0, s, a);
+  else hipLaunchKernelGGL((k_ifcm_gather<C, M2, NW, false, PT>), dim3(grid), dim3(64 * NW), 0, s, a);
   return hipGetLastError();
 }
 
-template <int C, bool M2, int NW>
+template <int C, bool M2, int NW, int PT>
 static int occ_gather_ct(bool step) {
   int n = 0;
-  const void* f = step ? reinterpret_cast<const void*>(&k_ifcm_gather<C, M2, NW, true>)
-                       : reinterpret_cast<const void*>(&k_ifcm_gather<C, M2, NW, false>);
+  const void* f = step ? reinterpret_cast<const void*>(&k_ifcm_gather<C, M2, NW, true, PT>)
+                       : reinterpret_cast<const void*>(&k_ifcm_gather<C, M2, NW, false, PT>);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64 * NW, 0) != hipSuccess) n = 1;
   return std::max(n, 1);
+}
+
+template <int C, int NW, int PT>
+static hipError_t launch_gather_m(const LaunchArgs& a, int grid, bool m2, bool step, hipStream_t s) {
+  return m2 ? launch_gather_ct<C, true, NW, PT>(a, grid, step, s) : launch_gather_ct<C, false, NW, PT>(a, grid, step, s);
+}
+
+template <int C, int NW, int PT>
+static int occ_gather_m(bool m2, bool step) {
+  return m2 ? occ_gather_ct<C, true, NW, PT>(step) : occ_gather_ct<C, false, NW, PT>(step);
 }
 
 template <int C, bool ALL_NW>
 static hipError_t launch_gather_one(const LaunchArgs& a, int grid, int nw, bool m2, bool step,
                                     hipStream_t s) {
   if constexpr (ALL_NW) {
+    if (a.pt == 2) {
+      switch (nw) {
+        case 1: return launch_gather_m<C, 1, 2>(a, grid, m2, step, s);
+        case 2: return launch_gather_m<C, 2, 2>(a, grid, m2, step, s);
+        case 4: return launch_gather_m<C, 4, 2>(a, grid, m2, step, s);
+        default: return hipErrorInvalidValue;
+      }
+    }
+    if (a.pt != 1) return hipErrorInvalidValue;
     switch (nw) {
-      case 1: return m2 ? launch_gather_ct<C, true, 1>(a, grid, step, s) : launch_gather_ct<C, false, 1>(a, grid, step, s);
-      case 2: return m2 ? launch_gather_ct<C, true, 2>(a, grid, step, s) : launch_gather_ct<C, false, 2>(a, grid, step, s);
-      case 4: return m2 ? launch_gather_ct<C, true, 4>(a, grid, step, s) : launch_gather_ct<C, false, 4>(a, grid, step, s);
+      case 1: return launch_gather_m<C, 1, 1>(a, grid, m2, step, s);
+      case 2: return launch_gather_m<C, 2, 1>(a, grid, m2, step, s);
+      case 4: return launch_gather_m<C, 4, 1>(a, grid, m2, step, s);
       default: return hipErrorInvalidValue;
     }
   } else {
-    if (nw != 4) return hipErrorInvalidValue;
-    return m2 ? launch_gather_ct<C, true, 4>(a, grid, step, s) : launch_gather_ct<C, false, 4>(a, grid, step, s);
+    if (nw != 4 || a.pt != 1) return hipErrorInvalidValue;
+    return launch_gather_m<C, 4, 1>(a, grid, m2, step, s);
   }
 }
 
 template <int C, bool ALL_NW>
-static int occ_gather_one(int nw, bool m2, bool step) {
+static int occ_gather_one(int nw, int pt, bool m2, bool step) {
   if constexpr (ALL_NW) {
+    if (pt == 2) {
+      switch (nw) {
+        case 1: return occ_gather_m<C, 1, 2>(m2, step);
+        case 2: return occ_gather_m<C, 2, 2>(m2, step);
+        case 4: return occ_gather_m<C, 4, 2>(m2, step);
+        default: return 1;
+      }
+    }
     switch (nw) {
-      case 1: return m2 ? occ_gather_ct<C, true, 1>(step) : occ_gather_ct<C, false, 1>(step);
-      case 2: return m2 ? occ_gather_ct<C, true, 2>(step) : occ_gather_ct<C, false, 2>(step);
-      case 4: return m2 ? occ_gather_ct<C, true, 4>(step) : occ_gather_ct<C, false, 4>(step);
+      case 1: return occ_gather_m<C, 1, 1>(m2, step);
+      case 2: return occ_gather_m<C, 2, 1>(m2, step);
+      case 4: return occ_gather_m<C, 4, 1>(m2, step);
       default: return 1;
     }
   } else {
-    return m2 ? occ_gather_ct<C, true, 4>(step) : occ_gather_ct<C, false, 4>(step);
+    return occ_gather_m<C, 4, 1>(m2, step);
   }
 }
 
@@ -512,6 +615,6 @@ static int occ_gather_one(int nw, bool m2, bool step) {
                                 hipStream_t s) {                                           \
     return launch_gather_one<c, all_nw>(a, grid, nw, m2, step, s);                         \
   }                                                                                        \
-  int occ_gather_C##c(int nw, bool m2, bool step) { return occ_gather_one<c, all_nw>(nw, m2, step); }
+  int occ_gather_C##c(int nw, int pt, bool m2, bool step) { return occ_gather_one<c, all_nw>(nw, pt, m2, step); }
 
 }  // namespace pifcm

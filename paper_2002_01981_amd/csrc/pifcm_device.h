@@ -69,8 +69,8 @@ struct RingOff {
 
 // Arguments of a fused launch over volumes [0, nvol) x particles [0, P).
 // Pairs are ordered volume-major: pair (b, p) = pairs[b * P + p]; work items
-// are ordered pair-major then tile, so adjacent tiles of one pair are
-// neighbours in item order.
+// are ordered pair-major (particle-group-major for the fused step) then
+// tile, so adjacent tiles of one pair are neighbours in item order.
 struct LaunchArgs {
   const VolDev* vols;
   const PairDev* pairs;
@@ -84,6 +84,9 @@ struct LaunchArgs {
   const RingOff* ring; // general-neighbourhood offsets (ring kernel only)
   int32_t nring;       // number of offsets
   int32_t pad1;
+  int32_t pt;          // particles per work item of the fused step (1 or 2):
+                       // its items are (volume, group of pt particles, tile)
+  int32_t pad2;
   float W[kMaxRings + 1];  // eq (10) weight of ring r at W[r]
 };
 

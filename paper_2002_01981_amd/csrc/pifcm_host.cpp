@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -38,6 +39,7 @@ struct GraphCache {
 struct TileShape {
   int nw = 4;   // wavefronts per work group of the fused step
   int zc = 32;  // planes per tile
+  int pt = 1;   // particles per work item of the batched fused step (C = 4: 1 or 2)
 };
 
 constexpr int kChunk = 8;            // iterations between stop-flag reads
@@ -55,7 +57,7 @@ struct pifcm_ctx {
   int num_cu = 256;
   DevBuf invg, rinv, ubuf, partials, states, jhist, tvol, tpair, flags;
   DevBuf adj_ck, adj_seg, adj_bar, adj_pq, adj_misc, adj_rs;  // ifcm_backward workspace
-  DevBuf tune_u0, tune_state;                          // pifcm_tune workspace
+  DevBuf tune_u0, tune_state, tune_ref;                // pifcm_tune workspace
   DevBuf ring_tab;                                     // general-neighbourhood offsets
   DevBuf conf;                                         // pifcm_confusion counts
   DevBuf pso_state;                                    // pifcm_pso_interleaved states
@@ -71,6 +73,7 @@ struct pifcm_ctx {
   double step_ms = 0.0;
   int64_t step_launches = 0;
   std::map<std::tuple<int, int, int, int, int>, TileShape> tuned;  // (C, m2, nx, ny, nz)
+  char arch[64] = "unknown";  // device architecture (tuning cache key)
 };
 
 namespace {
@@ -258,6 +261,27 @@ int grid_for(pifcm_ctx* ctx, int nitems, int occupancy, int per_group = 1) {
   return (int)std::max<long>(8, g);
 }
 
+// g_inv of `nv` volumes into invg (volume b at invg + invg_off[b]), the
+// intensity check, and the row check of caller U0 pointers (optional), with
+// flags (device, 2 ints) and stage (host, 2 ints) as workspace.
+pifcm_status run_invariants(pifcm_ctx* ctx, const pifcm_volume* vols, int nv, int C,
+                            const float* const* U0s, float* invg, const size_t* invg_off, int* flags,
+                            int* stage) {
+  HIPCHK(hipMemsetAsync(flags, 0, 2 * sizeof(int), ctx->s));
+  for (int b = 0; b < nv; ++b) {
+    HIPCHK(launch_invariants(vols[b].x, invg + invg_off[b], vols[b].nx, vols[b].ny, vols[b].nz,
+                             flags, ctx->s));
+    if (U0s && U0s[b]) HIPCHK(launch_check_rows(U0s[b], nvox(vols[b]), C, flags + 1, ctx->s));
+  }
+  HIPCHK(hipMemcpyAsync(stage, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->s));
+  HIPCHK(hipStreamSynchronize(ctx->s));
+  if (stage[0]) return fail(ctx, PIFCM_E_NONFINITE, "a volume holds a NaN or Inf intensity");
+  if (stage[1])
+    return fail(ctx, PIFCM_E_INVALID,
+                "initial memberships must be finite, in [0, 1] and sum to 1 (+-1e-4) per voxel");
+  return PIFCM_OK;
+}
+
 // Set up invariants of `nv` volumes into ctx->invg (concatenated) and check
 // intensities; optionally check rows of caller U0 pointers.
 pifcm_status prepare_volumes(pifcm_ctx* ctx, const pifcm_volume* vols, int nv, int C,
@@ -280,23 +304,9 @@ pifcm_status prepare_volumes(pifcm_ctx* ctx, const pifcm_volume* vols, int nv, i
                                      ctx->s));
   }
   TRY(ensure(ctx, ctx->flags, 64, "flags"));
-  int* flags = (int*)ctx->flags.p;
-  HIPCHK(hipMemsetAsync(flags, 0, 64, ctx->s));
-  float* invg = (float*)ctx->invg.p;
-  for (int b = 0; b < nv; ++b) {
-    HIPCHK(launch_invariants(vols[b].x, invg + invg_off[b], vols[b].nx, vols[b].ny, vols[b].nz,
-                             flags, ctx->s));
-    if (U0s && U0s[b]) HIPCHK(launch_check_rows(U0s[b], nvox(vols[b]), C, flags + 1, ctx->s));
-  }
   TRY(ensure_pinned(ctx, 4096));
-  HIPCHK(hipMemcpyAsync(ctx->pinned, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->s));
-  HIPCHK(hipStreamSynchronize(ctx->s));
-  const int* hf = (const int*)ctx->pinned;
-  if (hf[0]) return fail(ctx, PIFCM_E_NONFINITE, "a volume holds a NaN or Inf intensity");
-  if (hf[1])
-    return fail(ctx, PIFCM_E_INVALID,
-                "initial memberships must be finite, in [0, 1] and sum to 1 (+-1e-4) per voxel");
-  return PIFCM_OK;
+  return run_invariants(ctx, vols, nv, C, U0s, (float*)ctx->invg.p, invg_off.data(), (int*)ctx->flags.p,
+                        (int*)ctx->pinned);
 }
 
 SolveState init_state(const float* c0, int C, float lam, float xi, const pifcm_params* p,
@@ -333,11 +343,17 @@ int kind_of(const pifcm_params* p, bool zero_weights) {
   return ring_params(p) ? (ring2_params(p) ? kRing2 : kRing) : kGather;
 }
 
-int occupancy_of(int kind, int C, int nw, bool m2, bool step) {
+int occupancy_of(int kind, int C, int nw, bool m2, bool step, int pt = 1) {
   if (kind == kFcm) return fcm_occupancy(C, m2, step);
   if (kind == kRing) return ring_occupancy(C, m2, step);
   if (kind == kRing2) return ring2_occupancy(C, m2, step);
-  return gather_occupancy(C, nw, m2, step);
+  return gather_occupancy(C, nw, pt, m2, step);
+}
+
+// Particles per work item a launch of `kind` over P particles uses: the
+// shape's pt for the fused step of a swarm at C = 4, else 1.
+int pt_for(int kind, int C, int P, const TileShape& ts) {
+  return (kind == kGather && C == 4 && P >= 2) ? std::max(1, std::min(ts.pt, 2)) : 1;
 }
 
 // Work items in flight per work group.
@@ -409,8 +425,8 @@ hipError_t launch_step(int C, const LaunchArgs& a, int grid, int nw, bool m2, in
 }
 
 LaunchArgs make_args(const pifcm_ctx* ctx, const VolDev* vols_dev, const PairDev* pairs_dev,
-                     const std::vector<VolDev>& vh, int nvol, int P, int kind,
-                     const pifcm_params* p) {
+                     const VolDev* vh, int nvol, int P, int kind, const pifcm_params* p,
+                     int pt = 1) {
   LaunchArgs a;
   std::memset(&a, 0, sizeof a);
   a.vols = vols_dev;
@@ -426,20 +442,115 @@ LaunchArgs make_args(const pifcm_ctx* ctx, const VolDev* vols_dev, const PairDev
     a.pad1 = ctx->ring_gen;  // part of the graph cache key
     for (int r = 0; r <= kMaxRings; ++r) a.W[r] = ctx->ring_W[r];
   }
+  // Fused-step items are (volume, group of pt particles, tile).
+  a.pt = kind == kGather ? std::max(1, pt) : 1;
+  const int groups = (P + a.pt - 1) / a.pt;
   int acc = 0;
   for (int b = 0; b < nvol; ++b) {
     a.item_begin[b] = acc;
-    acc += P * (a.use_1d ? vh[b].tiles1d : vh[b].tiles);
+    acc += groups * (a.use_1d ? vh[b].tiles1d : vh[b].tiles);
   }
   a.item_begin[nvol] = acc;
   a.nitems = acc;
   return a;
 }
 
+LaunchArgs make_args(const pifcm_ctx* ctx, const VolDev* vols_dev, const PairDev* pairs_dev,
+                     const std::vector<VolDev>& vh, int nvol, int P, int kind,
+                     const pifcm_params* p, int pt = 1) {
+  return make_args(ctx, vols_dev, pairs_dev, vh.data(), nvol, P, kind, p, pt);
+}
+
 bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
   const char* pa = (const char*)a;
   const char* pb = (const char*)b;
   return pa < pb + nb && pb < pa + na;
+}
+
+// ------------------------------------------------------------ tuning cache
+// The tuner's choices are kept, if PIFCM_TUNE_CACHE names a file, as a JSON
+// object with one entry per line:
+//   "gfx950|C4|m2|V1|B6|P64|N2^25|Z2^7": {"nw": 4, "zc": 128, "pt": 2, "step_ms": 14.5},
+// keyed by device architecture, C, m == 2, V, the batch size, the particle
+// count and the total voxel count and largest plane count rounded up to
+// powers of two.
+int ceil_log2(double v) {
+  int k = 0;
+  while (std::ldexp(1.0, k) < v) ++k;
+  return k;
+}
+
+std::string tune_key(const pifcm_ctx* ctx, const pifcm_volume* vols, int B, const pifcm_params* p, int P) {
+  double n = 0.0;
+  int z = 1;
+  for (int b = 0; b < B; ++b) {
+    n += (double)nvox(vols[b]);
+    z = std::max(z, vols[b].nz);
+  }
+  char k[160];
+  snprintf(k, sizeof k, "%s|C%d|m%s|V%d|B%d|P%d|N2^%d|Z2^%d", ctx->arch, p->C, p->m == 2.0f ? "2" : "x", p->V, B,
+           P, ceil_log2(n), ceil_log2((double)z));
+  return k;
+}
+
+// Entries of the cache file as (key, rest of the line).
+std::vector<std::pair<std::string, std::string>> tune_cache_read(const char* path) {
+  std::vector<std::pair<std::string, std::string>> out;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return out;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    const char* a = std::strchr(line, '"');
+    if (!a) continue;
+    const char* b = std::strchr(a + 1, '"');
+    const char* c = b ? std::strchr(b, '{') : nullptr;
+    const char* d = c ? std::strchr(c, '}') : nullptr;
+    if (!d) continue;
+    out.emplace_back(std::string(a + 1, b), std::string(c, d + 1));
+  }
+  std::fclose(f);
+  return out;
+}
+
+bool tune_cache_get(const char* path, const std::string& key, TileShape& t, double& ms) {
+  for (const auto& e : tune_cache_read(path)) {
+    if (e.first != key) continue;
+    int nw = 0, zc = 0, pt = 0;
+    double m = 0.0;
+    if (std::sscanf(e.second.c_str(), "{\"nw\": %d, \"zc\": %d, \"pt\": %d, \"step_ms\": %lf}", &nw, &zc, &pt,
+                    &m) != 4)
+      return false;
+    if ((nw != 1 && nw != 2 && nw != 4) || zc < 1 || (pt != 1 && pt != 2)) return false;
+    t.nw = nw;
+    t.zc = zc;
+    t.pt = pt;
+    ms = m;
+    return true;
+  }
+  return false;
+}
+
+// Add or replace `key` (written to a temporary file, then renamed).
+void tune_cache_put(const char* path, const std::string& key, const TileShape& t, double ms) {
+  auto entries = tune_cache_read(path);
+  char val[160];
+  snprintf(val, sizeof val, "{\"nw\": %d, \"zc\": %d, \"pt\": %d, \"step_ms\": %.4f}", t.nw, t.zc, t.pt, ms);
+  bool found = false;
+  for (auto& e : entries)
+    if (e.first == key) {
+      e.second = val;
+      found = true;
+    }
+  if (!found) entries.emplace_back(key, val);
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  std::fprintf(f, "{\n");
+  for (size_t i = 0; i < entries.size(); ++i)
+    std::fprintf(f, "\"%s\": %s%s\n", entries[i].first.c_str(), entries[i].second.c_str(),
+                 i + 1 < entries.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  if (std::fclose(f) == 0) std::rename(tmp.c_str(), path);
 }
 
 }  // namespace
@@ -468,7 +579,16 @@ pifcm_status pifcm_create(int device, void* hip_stream, pifcm_ctx** out) {
     return PIFCM_E_HIP;
   }
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    ctx->num_cu = prop.multiProcessorCount;
+    // "gfx950:sramecc+:xnack-" -> "gfx950"
+    size_t n = 0;
+    while (n + 1 < sizeof ctx->arch && prop.gcnArchName[n] && prop.gcnArchName[n] != ':') {
+      ctx->arch[n] = prop.gcnArchName[n];
+      ++n;
+    }
+    ctx->arch[n] = 0;
+  }
   ensure(ctx, ctx->tvol, sizeof(VolDev) * kMaxBatchVols, "volume table");
   ensure(ctx, ctx->tpair, sizeof(PairDev) * kMaxPairs, "pair table");
   *out = ctx;
@@ -483,7 +603,7 @@ void pifcm_destroy(pifcm_ctx* ctx) {
   if (ctx->graph.graph) (void)hipGraphDestroy(ctx->graph.graph);
   for (DevBuf* b : {&ctx->invg, &ctx->rinv, &ctx->ubuf, &ctx->partials, &ctx->states, &ctx->jhist, &ctx->tvol,
                     &ctx->tpair, &ctx->flags, &ctx->adj_ck, &ctx->adj_seg, &ctx->adj_bar,
-                    &ctx->adj_pq, &ctx->adj_misc, &ctx->adj_rs, &ctx->tune_u0, &ctx->tune_state, &ctx->ring_tab,
+                    &ctx->adj_pq, &ctx->adj_misc, &ctx->adj_rs, &ctx->tune_u0, &ctx->tune_state, &ctx->tune_ref, &ctx->ring_tab,
                     &ctx->conf, &ctx->pso_state})
     if (b->p) (void)hipFree(b->p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -531,7 +651,7 @@ pifcm_status pifcm_workspace_bytes(pifcm_ctx* ctx, int64_t* device_bytes, int64_
   for (const DevBuf* b : {&ctx->invg, &ctx->rinv, &ctx->ubuf, &ctx->partials, &ctx->states, &ctx->jhist,
                           &ctx->tvol, &ctx->tpair, &ctx->flags, &ctx->adj_ck, &ctx->adj_seg,
                           &ctx->adj_bar, &ctx->adj_pq, &ctx->adj_misc, &ctx->adj_rs, &ctx->tune_u0,
-                          &ctx->tune_state, &ctx->ring_tab, &ctx->conf, &ctx->pso_state})
+                          &ctx->tune_state, &ctx->tune_ref, &ctx->ring_tab, &ctx->conf, &ctx->pso_state})
     d += (int64_t)b->cap;
   if (device_bytes) *device_bytes = d;
   if (pinned_bytes) *pinned_bytes = (int64_t)ctx->pinned_cap;
@@ -590,58 +710,73 @@ pifcm_status pifcm_normalize(pifcm_ctx* ctx, const float* raw, int64_t n, float*
 
 namespace {
 
-// One IFCM solve on the context's stream; shared by ifcm_solve and
-// pifcm_fcm_init.  U_final_out receives U^(T); host outputs optional.
-pifcm_status solve_impl(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
-                        float lambda, float xi, const float* centres_in, const float* U_in,
-                        float* U_out, float* centres_out, uint8_t* labels_out, double* J_out,
-                        int32_t* iters_out, double* J_hist_out, int zbeg = 0, int zend = -1) {
-  if (zend < 0) zend = vol->nz;
+// Memory one IFCM solve of a single volume works in.
+struct SolveWs {
+  float* invg = nullptr;       // device [N] g_inv
+  float* rinv = nullptr;       // device [N][4] ring invariants (two-ring kernel only)
+  float* ubuf = nullptr;       // device [N][C] second membership buffer
+  float* partials = nullptr;   // device [tiles][2C + 1] tile sums
+  SolveState* st = nullptr;    // device, one
+  PairDev* tpair = nullptr;    // device, one
+  VolDev* tvol = nullptr;      // device, one
+  double* jhist = nullptr;     // device [max(1, max_iter)]
+  int* flags = nullptr;        // device, 2 ints
+  char* stage = nullptr;       // host, kStageBytes (pinned or pageable)
+  double* jh_stage = nullptr;  // host [max_iter] staging of the J history, or NULL to copy
+                               // it straight into the caller's array
+};
+constexpr size_t kStageBytes = (sizeof(SolveState) + sizeof(PairDev) + sizeof(VolDev) + 64 + 255) / 256 * 256;
+
+// Tile slots of a solve over planes [zbeg, zend) (the larger of the tiled and
+// pointwise decompositions).
+int solve_slots(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p, int zbeg, int zend) {
+  const VolDev v = make_vol(*vol, nullptr, shape_for(ctx, p->C, p->m == 2.0f, *vol), zbeg, zend);
+  return std::max(v.tiles, v.tiles1d);
+}
+
+// One IFCM solve on the context's stream in the workspace ws.  U_out
+// receives U^(T); host outputs optional.
+pifcm_status solve_run(pifcm_ctx* ctx, const SolveWs& ws, const pifcm_volume* vol,
+                       const pifcm_params* p, float lambda, float xi, const float* centres_in,
+                       const float* U_in, float* U_out, float* centres_out, uint8_t* labels_out,
+                       double* J_out, int32_t* iters_out, double* J_hist_out, int zbeg, int zend) {
   const bool slab = zbeg > 0 || zend < vol->nz;
   const int C = p->C;
   const bool m2 = p->m == 2.0f;
   const int kind = kind_of(p, lambda == 0.0f && xi == 0.0f);
   const size_t N = nvox(*vol);
-  if (is_ring(kind)) TRY(prepare_ring(ctx, p));
-  std::vector<size_t> off;
+  if (kind == kRing2)
+    HIPCHK(launch_ring2_invariants(vol->x, ws.rinv, vol->nx, vol->ny, vol->nz,
+                                   (p->flags & PIFCM_Q2_SQDIST) ? 1 : 0, ctx->s));
+  const size_t off0 = 0;
   const float* u0s[1] = {U_in};
-  TRY(prepare_volumes(ctx, vol, 1, C, u0s, off, kind == kRing2 ? p : nullptr));
+  TRY(run_invariants(ctx, vol, 1, C, u0s, ws.invg, &off0, ws.flags, (int*)ws.stage));
   const TileShape ts = shape_for(ctx, C, m2, *vol);
-  std::vector<VolDev> vh{make_vol(*vol, (const float*)ctx->invg.p, ts, zbeg, zend,
-                                  kind == kRing2 ? (const float*)ctx->rinv.p : nullptr)};
-  const int slots = std::max(vh[0].tiles, vh[0].tiles1d);
-  TRY(ensure(ctx, ctx->ubuf, N * C * sizeof(float), "memberships"));
-  TRY(ensure(ctx, ctx->partials, (size_t)slots * (2 * C + 1) * sizeof(float), "tile sums"));
-  TRY(ensure(ctx, ctx->states, sizeof(SolveState), "solve state"));
-  TRY(ensure(ctx, ctx->jhist, (size_t)std::max(1, p->max_iter) * sizeof(double), "objective history"));
-  TRY(ensure_pinned(ctx, sizeof(SolveState) + sizeof(PairDev) + sizeof(VolDev) +
-                             (size_t)std::max(1, p->max_iter) * sizeof(double) + 4096));
-  SolveState* st_dev = (SolveState*)ctx->states.p;
-  float* ubuf = (float*)ctx->ubuf.p;
+  const VolDev vh = make_vol(*vol, ws.invg, ts, zbeg, zend, kind == kRing2 ? ws.rinv : nullptr);
   PairDev pr{};
-  pr.U0 = U_in ? U_in : ubuf;
+  pr.U0 = U_in ? U_in : ws.ubuf;
   pr.Ua = U_out;
-  pr.Ub = ubuf;
-  pr.st = st_dev;
-  pr.partials = (float*)ctx->partials.p;
+  pr.Ub = ws.ubuf;
+  pr.st = ws.st;
+  pr.partials = ws.partials;
 
-  char* pin = (char*)ctx->pinned;
-  SolveState hs = init_state(centres_in, C, lambda, xi, p, (double*)ctx->jhist.p);
+  char* pin = ws.stage;
+  SolveState hs = init_state(centres_in, C, lambda, xi, p, ws.jhist);
   std::memcpy(pin, &hs, sizeof hs);
   std::memcpy(pin + sizeof(SolveState), &pr, sizeof pr);
-  std::memcpy(pin + sizeof(SolveState) + sizeof(PairDev), &vh[0], sizeof(VolDev));
-  HIPCHK(hipMemcpyAsync(st_dev, pin, sizeof hs, hipMemcpyHostToDevice, ctx->s));
-  HIPCHK(hipMemcpyAsync(ctx->tpair.p, pin + sizeof(SolveState), sizeof pr, hipMemcpyHostToDevice, ctx->s));
-  HIPCHK(hipMemcpyAsync(ctx->tvol.p, pin + sizeof(SolveState) + sizeof(PairDev), sizeof(VolDev),
+  std::memcpy(pin + sizeof(SolveState) + sizeof(PairDev), &vh, sizeof(VolDev));
+  HIPCHK(hipMemcpyAsync(ws.st, pin, sizeof hs, hipMemcpyHostToDevice, ctx->s));
+  HIPCHK(hipMemcpyAsync(ws.tpair, pin + sizeof(SolveState), sizeof pr, hipMemcpyHostToDevice, ctx->s));
+  HIPCHK(hipMemcpyAsync(ws.tvol, pin + sizeof(SolveState) + sizeof(PairDev), sizeof(VolDev),
                         hipMemcpyHostToDevice, ctx->s));
-  if (!U_in) HIPCHK(launch_init_u(C, vol->x, N, st_dev, p->m, m2, ubuf, ctx->s));
+  if (!U_in) HIPCHK(launch_init_u(C, vol->x, N, ws.st, p->m, m2, ws.ubuf, ctx->s));
   if (slab) {
     // Planes outside the slab keep U_in in both iteration buffers.
     HIPCHK(hipMemcpyAsync(U_out, U_in, N * C * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
-    HIPCHK(hipMemcpyAsync(ubuf, U_in, N * C * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+    HIPCHK(hipMemcpyAsync(ws.ubuf, U_in, N * C * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
   }
 
-  LaunchArgs a = make_args(ctx, (const VolDev*)ctx->tvol.p, (const PairDev*)ctx->tpair.p, vh, 1, 1, kind, p);
+  LaunchArgs a = make_args(ctx, ws.tvol, ws.tpair, &vh, 1, 1, kind, p);
   const int occ = occupancy_of(kind, C, ts.nw, m2, true);
   const int grid = grid_for(ctx, a.nitems, occ, items_per_group(kind, ts.nw));
   int t = 0;
@@ -652,7 +787,7 @@ pifcm_status solve_impl(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_par
     for (int i = 0; i < k; ++i) HIPCHK(launch_step(C, a, grid, ts.nw, m2, kind, true, ctx->s));
     t += k;
     if (p->eps > 0.f && t < p->max_iter) {
-      HIPCHK(hipMemcpyAsync(hst, st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, ctx->s));
+      HIPCHK(hipMemcpyAsync(hst, ws.st, sizeof(SolveState), hipMemcpyDeviceToHost, ctx->s));
       HIPCHK(hipStreamSynchronize(ctx->s));
       if (hst->stop) break;
     }
@@ -663,23 +798,60 @@ pifcm_status solve_impl(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_par
   const int occe = occupancy_of(kind, C, ts.nw, m2, false);
   HIPCHK(launch_step(C, ae, grid_for(ctx, a.nitems, occe, items_per_group(kind, ts.nw)), ts.nw, m2,
                      kind, false, ctx->s));
-  HIPCHK(hipMemcpyAsync(hst, st_dev, sizeof(SolveState), hipMemcpyDeviceToHost, ctx->s));
+  HIPCHK(hipMemcpyAsync(hst, ws.st, sizeof(SolveState), hipMemcpyDeviceToHost, ctx->s));
   HIPCHK(hipStreamSynchronize(ctx->s));
   const int T = hst->iter;
   TRY(timing_collect(ctx, t));
   const float* Ufin = u_state_of(pr, T);
   if (labels_out) HIPCHK(launch_labels(Ufin, N, C, labels_out, ctx->s));
   if (Ufin != U_out) HIPCHK(hipMemcpyAsync(U_out, Ufin, N * C * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
-  double* jh = (double*)(pin + sizeof(SolveState) + 1024);
+  double* jh = ws.jh_stage ? ws.jh_stage : J_hist_out;
   if (J_hist_out && T > 0)
-    HIPCHK(hipMemcpyAsync(jh, ctx->jhist.p, (size_t)T * sizeof(double), hipMemcpyDeviceToHost, ctx->s));
+    HIPCHK(hipMemcpyAsync(jh, ws.jhist, (size_t)T * sizeof(double), hipMemcpyDeviceToHost, ctx->s));
   HIPCHK(hipStreamSynchronize(ctx->s));
   if (centres_out)
     for (int j = 0; j < C; ++j) centres_out[j] = hst->c[T & 1][j];
   if (J_out) *J_out = hst->J_eval;
   if (iters_out) *iters_out = T;
-  if (J_hist_out && T > 0) std::memcpy(J_hist_out, jh, (size_t)T * sizeof(double));
+  if (J_hist_out && T > 0 && ws.jh_stage) std::memcpy(J_hist_out, jh, (size_t)T * sizeof(double));
   return PIFCM_OK;
+}
+
+// One IFCM solve in the context's workspace (allocated or grown here);
+// shared by ifcm_solve, ifcm_solve_slab and pifcm_fcm_init.
+pifcm_status solve_impl(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
+                        float lambda, float xi, const float* centres_in, const float* U_in,
+                        float* U_out, float* centres_out, uint8_t* labels_out, double* J_out,
+                        int32_t* iters_out, double* J_hist_out, int zbeg = 0, int zend = -1) {
+  if (zend < 0) zend = vol->nz;
+  const int C = p->C;
+  const int kind = kind_of(p, lambda == 0.0f && xi == 0.0f);
+  const size_t N = nvox(*vol);
+  const size_t Np = (N + 63) / 64 * 64;
+  if (is_ring(kind)) TRY(prepare_ring(ctx, p));
+  const int slots = solve_slots(ctx, vol, p, zbeg, zend);
+  TRY(ensure(ctx, ctx->invg, Np * sizeof(float), "iteration invariants"));
+  if (kind == kRing2) TRY(ensure(ctx, ctx->rinv, Np * 4 * sizeof(float), "ring invariants"));
+  TRY(ensure(ctx, ctx->flags, 64, "flags"));
+  TRY(ensure(ctx, ctx->ubuf, N * C * sizeof(float), "memberships"));
+  TRY(ensure(ctx, ctx->partials, (size_t)slots * (2 * C + 1) * sizeof(float), "tile sums"));
+  TRY(ensure(ctx, ctx->states, sizeof(SolveState), "solve state"));
+  TRY(ensure(ctx, ctx->jhist, (size_t)std::max(1, p->max_iter) * sizeof(double), "objective history"));
+  TRY(ensure_pinned(ctx, kStageBytes + (size_t)std::max(1, p->max_iter) * sizeof(double) + 4096));
+  SolveWs ws;
+  ws.invg = (float*)ctx->invg.p;
+  ws.rinv = kind == kRing2 ? (float*)ctx->rinv.p : nullptr;
+  ws.ubuf = (float*)ctx->ubuf.p;
+  ws.partials = (float*)ctx->partials.p;
+  ws.st = (SolveState*)ctx->states.p;
+  ws.tpair = (PairDev*)ctx->tpair.p;
+  ws.tvol = (VolDev*)ctx->tvol.p;
+  ws.jhist = (double*)ctx->jhist.p;
+  ws.flags = (int*)ctx->flags.p;
+  ws.stage = (char*)ctx->pinned;
+  ws.jh_stage = (double*)((char*)ctx->pinned + kStageBytes);
+  return solve_run(ctx, ws, vol, p, lambda, xi, centres_in, U_in, U_out, centres_out, labels_out, J_out,
+                   iters_out, J_hist_out, zbeg, zend);
 }
 
 pifcm_status check_solve_args(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
@@ -854,8 +1026,11 @@ pifcm_status swarm_core(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
   if (is_ring(kind)) TRY(prepare_ring(ctx, p));
   const VolDev* vdev = (const VolDev*)ctx->tvol.p;
   const PairDev* pdev = (const PairDev*)ctx->tpair.p;
-  const int occ = occupancy_of(kind, C, ts0.nw, m2, true);
-  const int occe = occupancy_of(kind, C, ts0.nw, m2, false);
+  // Particles per work item of the batched launch (the per-pair launches of
+  // the plain mode hold one particle).
+  const int pt = mode == PIFCM_SWARM_BATCHED ? pt_for(kind, C, P, ts0) : 1;
+  const int occ = occupancy_of(kind, C, ts0.nw, m2, true, pt);
+  const int occe = occupancy_of(kind, C, ts0.nw, m2, false, pt);
   const int ipg = items_per_group(kind, ts0.nw);
 
   int64_t launches = 0;
@@ -868,7 +1043,7 @@ pifcm_status swarm_core(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
   };
 
   if (mode == PIFCM_SWARM_BATCHED) {
-    LaunchArgs a = make_args(ctx, vdev, pdev, vh, B, P, kind, p);
+    LaunchArgs a = make_args(ctx, vdev, pdev, vh, B, P, kind, p, pt);
     const int grid = grid_for(ctx, a.nitems, occ, ipg);
     const int chunk = p->eps > 0.f ? std::min(kChunk, std::max(1, p->max_iter)) : std::max(1, p->max_iter);
     // Capture `chunk` fused launches once; replay until every pair stops.
@@ -1215,6 +1390,25 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
   return PIFCM_OK;
 }
 
+pifcm_status pifcm_set_decomposition(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
+                                     const pifcm_params* p, int32_t waves_per_group,
+                                     int32_t planes_per_tile, int32_t particles_per_item) {
+  if (!ctx) return PIFCM_E_INVALID;
+  ctx->err.clear();
+  if (!vols || B < 1 || B > kMaxBatchVols) return fail(ctx, PIFCM_E_INVALID, "B = %d outside [1, %d]", B, kMaxBatchVols);
+  TRY(check_params(ctx, p));
+  for (int b = 0; b < B; ++b) TRY(check_volume(ctx, &vols[b], p->C));
+  const int nw = waves_per_group, zc = planes_per_tile, pt = particles_per_item;
+  if (nw != 1 && nw != 2 && nw != 4) return fail(ctx, PIFCM_E_INVALID, "waves_per_group = %d: 1, 2 or 4", nw);
+  if (p->C != 4 && nw != 4) return fail(ctx, PIFCM_E_UNSUPPORTED, "waves_per_group = %d is built for C = 4 only", nw);
+  if (zc < 1) return fail(ctx, PIFCM_E_INVALID, "planes_per_tile = %d must be >= 1", zc);
+  if (pt != 1 && pt != 2) return fail(ctx, PIFCM_E_INVALID, "particles_per_item = %d: 1 or 2", pt);
+  if (p->C != 4 && pt != 1) return fail(ctx, PIFCM_E_UNSUPPORTED, "particles_per_item = 2 is built for C = 4 only");
+  for (int b = 0; b < B; ++b)
+    ctx->tuned[std::make_tuple(p->C, (int)(p->m == 2.0f), vols[b].nx, vols[b].ny, vols[b].nz)] = TileShape{nw, zc, pt};
+  return PIFCM_OK;
+}
+
 pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, const pifcm_params* p,
                         int32_t P, char* best_out, int32_t best_len) {
   if (!ctx) return PIFCM_E_INVALID;
@@ -1222,28 +1416,56 @@ pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
   if (!vols || B < 1 || B > kMaxBatchVols) return fail(ctx, PIFCM_E_INVALID, "B = %d outside [1, %d]", B, kMaxBatchVols);
   if (P < 1 || (long)B * P > kMaxPairs) return fail(ctx, PIFCM_E_INVALID, "P = %d out of range", P);
   TRY(check_params(ctx, p));
-  if (ring_params(p)) {
+  auto describe = [&](const char* text) {
     if (best_out && best_len > 0) {
-      std::strncpy(best_out, "general neighbourhood: fixed decomposition, nothing timed", (size_t)best_len - 1);
+      std::strncpy(best_out, text, (size_t)best_len - 1);
       best_out[best_len - 1] = 0;
     }
+  };
+  if (ring_params(p)) {
+    describe("general neighbourhood: fixed decomposition, nothing timed");
     return PIFCM_OK;
   }
   const int C = p->C;
   for (int b = 0; b < B; ++b) TRY(check_volume(ctx, &vols[b], C));
   const bool m2 = p->m == 2.0f;
+  auto apply = [&](const TileShape& t) {
+    for (int b = 0; b < B; ++b) ctx->tuned[std::make_tuple(C, (int)m2, vols[b].nx, vols[b].ny, vols[b].nz)] = t;
+  };
+  // A choice kept in the cache file for this device, parameters and shape
+  // bucket is applied without timing.
+  const std::string key = tune_key(ctx, vols, B, p, P);
+  const char* cache = std::getenv("PIFCM_TUNE_CACHE");
+  if (cache && *cache) {
+    TileShape t;
+    double ms = 0.0;
+    if (tune_cache_get(cache, key, t, ms)) {
+      apply(t);
+      char desc[512];
+      snprintf(desc, sizeof desc, "waves_per_group=%d planes_per_tile=%d particles_per_item=%d step_ms=%.4f cached [%s]",
+               t.nw, t.zc, t.pt, ms, key.c_str());
+      describe(desc);
+      return PIFCM_OK;
+    }
+  }
   // Initial memberships: eq (2) with the attraction factor 1 for evenly
   // spaced centres, one buffer per volume.
   size_t total = 0;
   std::vector<size_t> uoff(B);
+  int bmin = 0;  // the smallest volume: element-wise membership check
   for (int b = 0; b < B; ++b) {
     uoff[b] = total;
     total += (nvox(vols[b]) * C + 63) / 64 * 64;
+    if (nvox(vols[b]) < nvox(vols[bmin])) bmin = b;
   }
+  const size_t nmin = nvox(vols[bmin]) * C;
+  const size_t nmin_pad = (nmin + 63) / 64 * 64;
+  const int Pc = std::min(P, 2);  // particles of the membership check
   TRY(begin(ctx));
   TRY(ensure(ctx, ctx->tune_u0, total * sizeof(float), "tuning memberships"));
   TRY(ensure(ctx, ctx->tune_state, sizeof(SolveState), "tuning state"));
-  TRY(ensure_pinned(ctx, sizeof(SolveState) + 4096));
+  TRY(ensure(ctx, ctx->tune_ref, 2 * (size_t)Pc * nmin_pad * sizeof(float), "tuning reference memberships"));
+  TRY(ensure_pinned(ctx, std::max<size_t>(sizeof(SolveState), 2 * (size_t)Pc * nmin_pad * sizeof(float)) + 4096));
   std::vector<float> c0((size_t)B * C);
   for (int b = 0; b < B; ++b)
     for (int j = 0; j < C; ++j) c0[(size_t)b * C + j] = (float)(((double)j + 0.5) / C);
@@ -1275,87 +1497,109 @@ pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
   pt.max_iter = std::max(2, std::min(p->max_iter, 4));
   int maxz = 1;
   for (int b = 0; b < B; ++b) maxz = std::max(maxz, vols[b].nz);
-  struct Cand { int nw, zc; };
-  std::vector<Cand> cands;
-  cands.push_back({4, 32});  // the default decomposition: the reference
+  std::vector<TileShape> cands;
+  cands.push_back(TileShape{4, 32, 1});  // the default decomposition: the reference
   const int nws[3] = {1, 2, 4};
   const int zcs[5] = {8, 16, 32, 64, 128};
-  for (int nw : nws) {
-    if (C != 4 && nw != 4) continue;
-    for (int zc : zcs) {
-      if (zc / 2 >= maxz && zc != 8) continue;  // one candidate covers the whole column
-      if (nw == 4 && zc == 32) continue;
-      cands.push_back({nw, zc});
+  const int maxpt = (C == 4 && P >= 2) ? 2 : 1;
+  for (int ptc = 1; ptc <= maxpt; ++ptc)
+    for (int nw : nws) {
+      if (C != 4 && nw != 4) continue;
+      for (int zc : zcs) {
+        if (zc / 2 >= maxz && zc != 8) continue;  // one candidate covers the whole column
+        if (nw == 4 && zc == 32 && ptc == 1) continue;
+        cands.push_back(TileShape{nw, zc, ptc});
+      }
     }
-  }
   const bool was_timing = ctx->timing;
   const auto saved = ctx->tuned;
   std::vector<double> fit_ref((size_t)B * P), fit((size_t)B * P);
   std::vector<float> cen_ref((size_t)B * P * C), cen((size_t)B * P * C);
+  // Final memberships of the check: reference (candidate 0) in the first Pc
+  // buffers, the candidate's in the next Pc.
+  float* uref[2] = {(float*)ctx->tune_ref.p, (float*)ctx->tune_ref.p + nmin_pad};
+  float* ucand[2] = {(float*)ctx->tune_ref.p + Pc * nmin_pad, (float*)ctx->tune_ref.p + (Pc + 1) * nmin_pad};
+  const float* U0min[2] = {U0[bmin], U0[bmin]};
+  std::vector<float> cmin((size_t)Pc * C);
+  for (int q = 0; q < Pc; ++q)
+    for (int j = 0; j < C; ++j) cmin[(size_t)q * C + j] = c0[(size_t)bmin * C + j];
+  std::vector<double> fchk(Pc);
   double best_ms = 1e300;
-  Cand best = cands[0];
-  char desc[1024] = {0};
+  TileShape best = cands[0];
   std::string tried;
   for (size_t ci = 0; ci < cands.size(); ++ci) {
-    for (int b = 0; b < B; ++b) {
-      TileShape t;
-      t.nw = cands[ci].nw;
-      t.zc = cands[ci].zc;
-      ctx->tuned[std::make_tuple(C, (int)m2, vols[b].nx, vols[b].ny, vols[b].nz)] = t;
-    }
+    apply(cands[ci]);
     ctx->timing = false;
     pifcm_status st = swarm_evaluate(ctx, vols, B, &pt, parts.data(), P, c0.data(), U0.data(),
                                      fit.data(), cen.data(), nullptr, PIFCM_SWARM_BATCHED);
+    double ms = 0.0;
     if (st == PIFCM_OK) {
       ctx->timing = true;
       const double ms0 = ctx->step_ms;
       const int64_t n0 = ctx->step_launches;
       st = swarm_evaluate(ctx, vols, B, &pt, parts.data(), P, c0.data(), U0.data(), fit.data(),
                           cen.data(), nullptr, PIFCM_SWARM_BATCHED);
-      const double ms = (ctx->step_ms - ms0) / std::max<int64_t>(1, ctx->step_launches - n0);
+      ms = (ctx->step_ms - ms0) / std::max<int64_t>(1, ctx->step_launches - n0);
       ctx->step_ms = ms0;
       ctx->step_launches = n0;
-      if (st == PIFCM_OK) {
-        bool ok = true;
-        if (ci == 0) {
-          fit_ref = fit;
-          cen_ref = cen;
-        } else {
-          for (size_t k = 0; k < fit.size(); ++k)
-            ok = ok && std::fabs(fit[k] - fit_ref[k]) <= 1e-5 * std::fabs(fit_ref[k]);
-          for (size_t k = 0; k < cen.size(); ++k)
-            ok = ok && std::fabs(cen[k] - cen_ref[k]) <= 1e-5f * std::max(1e-3f, std::fabs(cen_ref[k]));
-        }
-        char one[48];
-        snprintf(one, sizeof one, "%s%dx%d:%.3f%s", tried.empty() ? "" : " ", cands[ci].nw, cands[ci].zc, ms,
-                 ok ? "" : "(differs)");
-        tried += one;
-        if (ok && ms < best_ms) {
-          best_ms = ms;
-          best = cands[ci];
-        }
-      }
     }
-    if (st != PIFCM_OK && ci == 0) {
-      ctx->timing = was_timing;
-      ctx->tuned = saved;
-      return st;
+    // Memberships of the first particles on the smallest volume, element
+    // by element (the same decomposition as the timed launch).
+    if (st == PIFCM_OK) {
+      ctx->timing = false;
+      st = swarm_core(ctx, &vols[bmin], 1, &pt, parts.data() + (size_t)bmin * P * 2, Pc, cmin.data(), U0min,
+                      nullptr, ci == 0 ? uref : ucand, fchk.data(), nullptr, nullptr, PIFCM_SWARM_BATCHED);
+    }
+    if (st != PIFCM_OK) {
+      if (ci == 0) {
+        ctx->timing = was_timing;
+        ctx->tuned = saved;
+        return st;
+      }
+      continue;
+    }
+    bool ok = true;
+    double du = 0.0;
+    if (ci == 0) {
+      fit_ref = fit;
+      cen_ref = cen;
+    } else {
+      for (size_t k = 0; k < fit.size(); ++k)
+        ok = ok && std::fabs(fit[k] - fit_ref[k]) <= 1e-5 * std::fabs(fit_ref[k]);
+      for (size_t k = 0; k < cen.size(); ++k)
+        ok = ok && std::fabs(cen[k] - cen_ref[k]) <= 1e-5f * std::max(1e-3f, std::fabs(cen_ref[k]));
+      float* hu = (float*)ctx->pinned;
+      HIPCHK(hipMemcpyAsync(hu, ctx->tune_ref.p, 2 * (size_t)Pc * nmin_pad * sizeof(float), hipMemcpyDeviceToHost,
+                            ctx->s));
+      HIPCHK(hipStreamSynchronize(ctx->s));
+      double dmax = 0.0, rmax = 0.0;
+      for (int q = 0; q < Pc; ++q)
+        for (size_t i = 0; i < nmin; ++i) {
+          const double r = hu[q * nmin_pad + i], c = hu[(Pc + q) * nmin_pad + i];
+          dmax = std::max(dmax, std::fabs(c - r));
+          rmax = std::max(rmax, std::fabs(r));
+        }
+      du = dmax / std::max(rmax, 1e-30);
+      ok = ok && du <= 1e-4;
+    }
+    char one[64];
+    snprintf(one, sizeof one, "%s%dx%dx%d:%.3f%s", tried.empty() ? "" : " ", cands[ci].nw, cands[ci].zc,
+             cands[ci].pt, ms, ok ? "" : "(differs)");
+    tried += one;
+    if (ok && ms < best_ms) {
+      best_ms = ms;
+      best = cands[ci];
     }
   }
   ctx->timing = was_timing;
   ctx->tuned = saved;
-  for (int b = 0; b < B; ++b) {
-    TileShape t;
-    t.nw = best.nw;
-    t.zc = best.zc;
-    ctx->tuned[std::make_tuple(C, (int)m2, vols[b].nx, vols[b].ny, vols[b].nz)] = t;
-  }
-  snprintf(desc, sizeof desc, "waves_per_group=%d planes_per_tile=%d step_ms=%.4f candidates=%zu [%s]",
-           best.nw, best.zc, best_ms, cands.size(), tried.c_str());
-  if (best_out && best_len > 0) {
-    std::strncpy(best_out, desc, (size_t)best_len - 1);
-    best_out[best_len - 1] = 0;
-  }
+  apply(best);
+  if (cache && *cache) tune_cache_put(cache, key, best, best_ms);
+  char desc[1024];
+  snprintf(desc, sizeof desc,
+           "waves_per_group=%d planes_per_tile=%d particles_per_item=%d step_ms=%.4f candidates=%zu [%s]", best.nw,
+           best.zc, best.pt, best_ms, cands.size(), tried.c_str());
+  describe(desc);
   ctx->err.clear();
   return PIFCM_OK;
 }

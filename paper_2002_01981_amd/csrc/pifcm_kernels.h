@@ -8,7 +8,8 @@
 namespace pifcm {
 
 // Fused IFCM step (step = true) or objective-only pass (step = false) over
-// the tiles of a launch; ty = rows per tile (2, 4 or 8).
+// the tiles of a launch; ty = waves per work group (1, 2 or 4; 4 unless
+// C = 4), a.pt = particles per work item (1, or 2 at C = 4).
 hipError_t launch_gather(int C, const LaunchArgs& a, int grid, int ty, bool m2, bool step,
                          hipStream_t s);
 // Per-pair fp64 sum of the tile slots of the preceding step / objective
@@ -72,7 +73,7 @@ hipError_t launch_adjoint(int C, const AdjArgs& a, bool m2, bool eval, float* Ub
 size_t adjoint_slots(int nx, int ny, int nz);
 
 // Resident work groups per CU of the gather / pointwise kernels.
-int gather_occupancy(int C, int ty, bool m2, bool step);
+int gather_occupancy(int C, int ty, int pt, bool m2, bool step);
 int fcm_occupancy(int C, bool m2, bool step);
 
 }  // namespace pifcm

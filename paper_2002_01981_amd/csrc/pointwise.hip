@@ -271,7 +271,7 @@ static hipError_t launch_init_c(const float* x, size_t N, const SolveState* st, 
 #define DECL(c)                                                                              \
   hipError_t launch_gather_C##c(const LaunchArgs& a, int grid, int ty, bool m2, bool step, \
                                 hipStream_t s);                                            \
-  int occ_gather_C##c(int ty, bool m2, bool step);
+  int occ_gather_C##c(int ty, int pt, bool m2, bool step);
 PIFCM_FOR_EACH_C(DECL)
 #undef DECL
 
@@ -286,10 +286,10 @@ hipError_t launch_gather(int C, const LaunchArgs& a, int grid, int ty, bool m2, 
   }
 }
 
-int gather_occupancy(int C, int ty, bool m2, bool step) {
+int gather_occupancy(int C, int ty, int pt, bool m2, bool step) {
   switch (C) {
 #define CASE(c) \
-  case c: return occ_gather_C##c(ty, m2, step);
+  case c: return occ_gather_C##c(ty, pt, m2, step);
     PIFCM_FOR_EACH_C(CASE)
 #undef CASE
     default: return 1;

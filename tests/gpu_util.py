@@ -25,6 +25,49 @@ def saturated(lam, xi):
     return lam + xi > 1.0
 
 
+# One step from a given state is held to the max-norm bar on every voxel
+# whose attraction factor a_ij = 1 - lambda H_ij - xi F_ij (eq (4)) is at
+# least A_MIN away from zero for every cluster.  Float32 rounding of a
+# (about 1e-6 after the 26-term sums of eqs (5), (7)) then moves a positive
+# d^2 by at most ~2e-5 relative, and cannot flip the sign of a negative one,
+# whose d^2 is the 1e-12 floor on both sides: a membership moves by less
+# than 1e-5.  Voxels with a factor near zero are ill-conditioned in either
+# precision (whether the floor engages, and by how much d^2 exceeds it,
+# depends on rounding; a float32 restatement of the step shows errors of
+# 1e-2 there, see test_fp32_conditioning.py): they are checked for valid
+# memberships and labels within the wide tie band.
+A_MIN = 0.05
+
+
+def regular_voxels(H, F, lam, xi, a_min=A_MIN):
+    """Per voxel: True where every cluster's eq (4) factor a satisfies
+    |a| >= a_min."""
+    a = 1.0 - lam * np.asarray(H) - xi * np.asarray(F)
+    return np.all(np.abs(a) >= a_min, axis=1)
+
+
+def check_step_memberships(Ug, lab_g, Uo, H, F, lam, xi, C, tol=TOL):
+    """One step from the same state on both sides: max-norm bar and the
+    narrow tie band on regular voxels; on the others (a factor of eq (4)
+    within A_MIN of zero) valid memberships and the wide tie band.  Returns
+    the number of irregular voxels."""
+    Ug = np.asarray(Ug, np.float64).reshape(-1, C)
+    Uo = np.asarray(Uo, np.float64).reshape(-1, C)
+    reg = regular_voxels(H, F, lam, xi)
+    scale = float(np.max(np.abs(Uo)))
+    if reg.any():
+        e = float(np.max(np.abs(Ug[reg] - Uo[reg]))) / scale
+        assert e <= tol, f"max-norm error {e:.3g} on regular voxels"
+    assert np.all(Ug >= 0.0) and np.all(Ug <= 1.0 + 1e-6)
+    assert np.max(np.abs(Ug.sum(1) - 1.0)) <= 1e-5
+    if lab_g is not None:
+        lab = np.asarray(lab_g).reshape(-1)
+        check_labels(lab[reg], Uo[reg], C, TIE_BAND)
+        if (~reg).any():
+            check_labels(lab[~reg], Uo[~reg], C, SATURATED_TIE_BAND)
+    return int((~reg).sum())
+
+
 def rel2(a, ref):
     a = np.asarray(a, np.float64)
     ref = np.asarray(ref, np.float64)
