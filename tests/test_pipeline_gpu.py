@@ -94,7 +94,8 @@ def test_segment_nested32_matches_oracle(ctx):
                 continue
             n_held += 1
             assert abs(g["fit_hist"][gen, q] - o["J"]) <= TOL * abs(o["J"]), (gen, q)
-    assert n_held >= 5
+    print(f"evaluations held to the bar: {n_held} of {G * P}")
+    assert n_held >= 7
 
     # final solve at the best particle (Algorithm 1, step 11)
     lam, xi = (float(v) for v in np.float32(g["best_pos"]))
