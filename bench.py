@@ -18,6 +18,7 @@ the FP64 oracle's rate on a bounded sample of the workload on this host.
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -65,24 +66,32 @@ def copy_bandwidth(torch, mib=1024, reps=5):
     return 2 * n * 4 / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(vol_raw, seconds):
+def cpu_baseline(vol_raw, seconds, threads=None):
     """The FP64 oracle, as it stands, on one (volume, particle) pair of the
-    workload: IFCM steps at (lambda, xi) = (0.3, 0.4) on this host's cores
-    until about `seconds` of work (whole steps, at least two)."""
+    workload: IFCM steps at (lambda, xi) = (0.3, 0.4) on `threads` host
+    threads (default: the oracle's own, all cores) until about `seconds` of
+    work (whole steps, at least two)."""
     import numpy as np
     import oracle
-    x = oracle.normalize(vol_raw)
-    p = oracle.Params(C=4, m=2.0, eps=0.0, max_iter=1)
-    c = np.array([0.125, 0.375, 0.625, 0.875])
-    U = oracle.init_memberships(x, c, p)
-    t0 = time.perf_counter()
-    U, c, _ = oracle.step(x, U, c, p, 0.3, 0.4)
-    one = time.perf_counter() - t0
-    iters = max(2, int(round(seconds / max(one, 1e-6))))
-    for _ in range(iters - 1):
+    before = oracle.get_threads()
+    if threads:
+        oracle.set_threads(threads)
+    try:
+        x = oracle.normalize(vol_raw)
+        p = oracle.Params(C=4, m=2.0, eps=0.0, max_iter=1)
+        c = np.array([0.125, 0.375, 0.625, 0.875])
+        U = oracle.init_memberships(x, c, p)
+        used = oracle.get_threads()
+        t0 = time.perf_counter()
         U, c, _ = oracle.step(x, U, c, p, 0.3, 0.4)
-    dt = time.perf_counter() - t0
-    return x.size * 4 * iters / dt, dt, iters, oracle.get_threads()
+        one = time.perf_counter() - t0
+        iters = max(2, int(round(seconds / max(one, 1e-6))))
+        for _ in range(iters - 1):
+            U, c, _ = oracle.step(x, U, c, p, 0.3, 0.4)
+        dt = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(before)
+    return x.size * 4 * iters / dt, dt, iters, used
 
 
 def adjoint_leg(Context, Params):
@@ -153,6 +162,69 @@ def ring_leg(Context, Params, vol_raw, dims):
                 algorithmic_GBps=round(per_launch / (avg * 1e-3) / 1e9, 1))
 
 
+def pso_leg(Context, Params, name, mode, noise=None):
+    """One full particle swarm search (Algorithm 1 steps 2-9: FCM start,
+    pifcm_pso with the workload's swarm, stop rule eps, max_iter) on a
+    workload of the paper's shapes, after one untimed run of the same
+    search.  Rates count the IFCM iterations the evaluations actually ran."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2002_01981_amd import PIFCM_SWARM_BATCHED
+    W = synth.WORKLOADS[name]
+    if W["kind"] == "nested":
+        raw, _ = synth.nested_ellipsoids(shape=W["shape"], seed=W["seed"], sigma=W["sigma"])
+    elif W["kind"] == "ellipsoids":
+        raw, _ = synth.random_ellipsoids(shape=W["shape"], seed=W["seed"], sigma=W["sigma"])
+    else:
+        raw, _ = synth.brain_shells(shape=W["shape"], seed=W["seed"], noise_frac=noise)
+    ps = W["pso"]
+    st = synth.pso_streams(ps["seed"], ps["P"], ps["G"])
+    p = Params(C=W["C"], m=W["m"], eps=W["eps"], max_iter=W["max_iter"])
+    ctx = Context(0)
+    x = ctx.pifcm_normalize(torch.from_numpy(raw).cuda())
+    c0, U0, _ = ctx.pifcm_fcm_init(x, p)
+
+    def run():
+        return ctx.pifcm_pso([x], p, st, c0[None], [U0], w=ps["w"], c1=ps["c1"], c2=ps["c2"],
+                             mode=mode)
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sw = run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.close()
+    n = int(np.prod(W["shape"]))
+    its = int(sw["iters_hist"].sum())
+    out = dict(workload=name if noise is None else f"{name} noise {noise:.0%}",
+               volume_zyx=list(W["shape"]), swarm=[ps["P"], ps["G"]], eps=W["eps"],
+               max_iter=W["max_iter"], mode="batched" if mode == PIFCM_SWARM_BATCHED else "plain",
+               seconds=round(dt, 4), evaluations=ps["P"] * ps["G"], iterations=its,
+               value=n * W["C"] * its / dt, unit="voxel-cluster-iters/s",
+               algorithmic_GBps=round(n * (8 * W["C"] + 4) * its / dt / 1e9, 1),
+               best_pos=[round(float(v), 4) for v in sw["best_pos"][0]])
+    return out
+
+
+def cpu_search(name):
+    """The FP64 oracle's whole swarm search (FCM start and pifcm_pso's
+    schedule) on a small workload: seconds and the iterations it ran."""
+    import oracle
+    import synth
+    W = synth.WORKLOADS[name]
+    raw, _ = synth.nested_ellipsoids(shape=W["shape"], seed=W["seed"], sigma=W["sigma"])
+    ps = W["pso"]
+    st = synth.pso_streams(ps["seed"], ps["P"], ps["G"])
+    xo = oracle.normalize(raw)
+    po = oracle.Params(C=W["C"], m=W["m"], eps=W["eps"], max_iter=W["max_iter"])
+    t0 = time.perf_counter()
+    c0, U0, _ = oracle.fcm_init(xo, po)
+    oracle.pso(xo, c0, U0, po, st, w=ps["w"], c1=ps["c1"], c2=ps["c2"])
+    return dict(workload=name, seconds=round(time.perf_counter() - t0, 4),
+                threads=oracle.get_threads())
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +238,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--no-ring", action="store_true", help="skip the general-neighbourhood leg")
+    ap.add_argument("--no-pso", action="store_true",
+                    help="skip the full swarm searches on the 32x32x8, 854x854x16 and brain volumes")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device copy of MIB MiB a few times (counter scaling)")
     args = ap.parse_args()
@@ -247,8 +321,13 @@ def main():
     value = work / (ms_step * 1e-3)
 
     # Roofline of the fused step: algorithmic bytes per launch = per voxel and
-    # particle, U^(t) read (4C B) + U^(t+1) written (4C B) + x read (4 B).
-    per_launch_bytes = sum(nvox) * P * (8 * C + 4)
+    # particle, U^(t) read (4C B) + U^(t+1) written (4C B) + x read (4 B),
+    # which a work item of pt particles reads once for all of them.
+    pt = 1
+    if tune is not None:
+        m = re.search(r"particles_per_item=(\d+)", tune["choice"])
+        pt = int(m.group(1)) if m else 1
+    per_launch_bytes = round(sum(nvox) * P * (8 * C + 4 / pt))
     avg_launch_ms = kern_ms / max(launches, 1)
     achieved = per_launch_bytes / (avg_launch_ms * 1e-3) / 1e9
     traffic = valu = None
@@ -273,6 +352,7 @@ def main():
                     frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=traffic,
                     kernel=KERNEL, avg_launch_us=round(avg_launch_ms * 1e3, 2),
                     launches=int(launches), algorithmic_bytes_per_launch=per_launch_bytes,
+                    algorithmic_bytes_per_voxel_particle=8 * C + 4 / pt, particles_per_item=pt,
                     # measured HBM bytes (counters) over the live launch time,
                     # and what a plain 1 GiB copy reaches in the same run
                     hbm_GBps_measured=(round(traffic / (avg_launch_ms * 1e-3) / 1e9, 1)
@@ -282,30 +362,43 @@ def main():
 
     plain = None
     if not args.no_plain and mode == PIFCM_SWARM_BATCHED:
-        # the plain mode runs one small launch per (volume, particle): it gets
-        # a context of its own with the default decomposition, not the tile
-        # shape tuned for the batched launch
+        # The plain mode runs one small launch per (volume, particle): it gets
+        # a context of its own with the default decomposition, not the shape
+        # tuned for the batched launch, and the batched launch is timed there
+        # too, so that the comparison isolates batching.
         ctx_b = ctx
         ctx = Context(0)
-        step(PIFCM_SWARM_PLAIN)
-        torch.cuda.synchronize()
-        ctx.pifcm_set_timing(True)
-        tp0 = time.perf_counter()
-        outp = step(PIFCM_SWARM_PLAIN)
-        torch.cuda.synchronize()
-        tp1 = time.perf_counter()
-        ctx.pifcm_set_timing(False)
-        pk_ms, pl = ctx.pifcm_get_timing(reset=True)
-        same = float(np.max(np.abs(outp["fitness"] / out["fitness"] - 1.0)))
+
+        def timed(m):
+            step(m)
+            torch.cuda.synchronize()
+            ctx.pifcm_get_timing(reset=True)
+            ctx.pifcm_set_timing(True)
+            ta = time.perf_counter()
+            o = step(m)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            ctx.pifcm_set_timing(False)
+            kms, nl = ctx.pifcm_get_timing(reset=True)
+            return o, (tb - ta) * 1e3, kms, nl
+
+        outd, bd_ms, bd_k, bd_n = timed(PIFCM_SWARM_BATCHED)
+        outp, pl_ms, pk_ms, pl = timed(PIFCM_SWARM_PLAIN)
+        same = float(np.max(np.abs(outp["fitness"] / outd["fitness"] - 1.0)))
+        tuned_diff = float(np.max(np.abs(outd["fitness"] / out["fitness"] - 1.0)))
         ctx.close()
         ctx = ctx_b
-        plain = dict(ms_per_step=round((tp1 - tp0) * 1e3, 3),
-                     value=work / (tp1 - tp0), launches_per_step=int(pl),
-                     avg_launch_us=round(pk_ms / max(pl, 1) * 1e3, 2),
-                     batched_speedup=round((tp1 - tp0) * 1e3 / ms_step, 3),
-                     max_rel_fitness_diff_vs_batched=same,
-                     decomposition="default (4 waves x 32 planes)")
-        log(f"plain: {(tp1 - tp0) * 1e3:.1f} ms/step, max rel diff {same:.2e}")
+        plain = dict(decomposition="default (4 waves x 32 planes, 1 particle per item)",
+                     ms_per_step=round(pl_ms, 3), value=work / (pl_ms * 1e-3),
+                     launches_per_step=int(pl), avg_launch_us=round(pk_ms / max(pl, 1) * 1e3, 2),
+                     batched_ms_per_step=round(bd_ms, 3),
+                     batched_avg_launch_us=round(bd_k / max(bd_n, 1) * 1e3, 2),
+                     batched_speedup=round(pl_ms / bd_ms, 3),
+                     max_rel_fitness_diff_plain_vs_batched=same,
+                     tuned_batched_speedup=round(pl_ms / ms_step, 3),
+                     max_rel_fitness_diff_default_vs_tuned=tuned_diff)
+        log(f"default decomposition: batched {bd_ms:.1f} ms/step, plain {pl_ms:.1f} ms/step, "
+            f"max rel diff {same:.2e}")
 
     ring = None
     if not args.no_ring:
@@ -318,14 +411,29 @@ def main():
         adjoint = adjoint_leg(Context, Params)
         log(f"adjoint: forward {adjoint['forward_ms']} ms, backward {adjoint['backward_ms']} ms")
 
+    pso = None
+    if not args.no_pso:
+        pso = [pso_leg(Context, Params, "nested-32x32x8", PIFCM_SWARM_BATCHED),
+               pso_leg(Context, Params, "ellipsoids-854x854x16", PIFCM_SWARM_PLAIN)]
+        pso += [pso_leg(Context, Params, "brain-181x217x181", PIFCM_SWARM_BATCHED, noise=f)
+                for f in (0.03, 0.05, 0.09)]
+        for leg in pso:
+            log(f"swarm search {leg['workload']}: {leg['seconds']} s, {leg['iterations']} iterations, "
+                f"{leg['value']:.3g} vci/s")
+
     cpu = None
     if not args.no_cpu_baseline:
         b = int(np.argmin(nvox))
         rate, dt, iters, cores = cpu_baseline(vols[b][0], args.cpu_seconds)
+        rate1, dt1, iters1, _ = cpu_baseline(vols[b][0], args.cpu_seconds / 3, threads=1)
         cpu = dict(value=rate, unit="voxel-cluster-iters/s", cores=cores, kind="oracle",
                    sample=f"volume {b} of the batch ({dims[b][2]}x{dims[b][1]}x{dims[b][0]}), "
-                          f"one particle (0.3, 0.4), {iters} IFCM steps in {dt:.1f} s")
-        log(f"cpu baseline: {rate:.3g} vci/s on {cores} threads in {dt:.1f}s")
+                          f"one particle (0.3, 0.4), {iters} IFCM steps in {dt:.1f} s",
+                   host_cpus=os.cpu_count(),
+                   one_thread=dict(value=rate1, steps=iters1, seconds=round(dt1, 2)),
+                   full_search=cpu_search("nested-32x32x8"))
+        log(f"cpu baseline: {rate:.3g} vci/s on {cores} threads in {dt:.1f}s; "
+            f"{rate1:.3g} vci/s on 1 thread; {os.cpu_count()} host CPUs")
 
     res = {
         "metric": METRIC,
@@ -354,6 +462,7 @@ def main():
         "plain": plain,
         "ring": ring,
         "adjoint": adjoint,
+        "swarm_searches": pso,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

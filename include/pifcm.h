@@ -222,12 +222,14 @@ pifcm_status pifcm_set_decomposition(pifcm_ctx* ctx, const pifcm_volume* vols, i
  * (host [G][P][2]) are the coefficients of generation g.  centres0, U0: the
  * shared initial state of each volume (as in swarm_evaluate).
  * Outputs (host): best_pos [B][2], best_fit [B], and optionally fit_hist
- * [B][G][P] and pos_hist [B][G][P][2] (positions evaluated). */
+ * [B][G][P], pos_hist [B][G][P][2] (positions evaluated) and iters_hist
+ * [B][G][P] (IFCM iterations each evaluation ran before its stop rule or
+ * max_iter ended it); NULL skips an optional output. */
 pifcm_status pifcm_pso(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, const pifcm_params* p,
                        int32_t P, int32_t G, const double* x0, const double* v0, const double* r1,
                        const double* r2, double w, double c1, double c2, const float* centres0,
                        const float* const* U0, int32_t mode, double* best_pos, double* best_fit,
-                       double* fit_hist, double* pos_hist);
+                       double* fit_hist, double* pos_hist, int32_t* iters_hist);
 
 /* The interleaved reading of the swarm schedule (Algorithm 2, step 11):
  * every particle carries its own IFCM state.  Particle q of volume b starts

@@ -115,7 +115,7 @@ def load_library(path=LIB_PATH):
     lib.pifcm_set_decomposition.restype = st
     lib.pifcm_pso.argtypes = [vp, P(_Volume), i32, P(_Params), i32, i32, P(f64), P(f64), P(f64),
                               P(f64), f64, f64, f64, P(f32), P(vp), i32, P(f64), P(f64), P(f64),
-                              P(f64)]
+                              P(f64), P(i32)]
     lib.pifcm_pso.restype = st
     lib.pifcm_pso_interleaved.argtypes = [vp, P(_Volume), i32, P(_Params), i32, i32, i32, P(f64),
                                           P(f64), P(f64), P(f64), f64, f64, f64, P(f32), P(vp),
@@ -405,7 +405,7 @@ class Context:
         """Global-best PSO on B volumes.  streams: dict(x0, v0 (P, 2), r1, r2
         (G, P, 2)); centres0 (B, C); U0s: list of B (N_b, C) tensors.
         Returns dict(best_pos (B, 2), best_fit (B,), fit_hist (B, G, P),
-        pos_hist (B, G, P, 2))."""
+        pos_hist (B, G, P, 2), iters_hist (B, G, P) iterations per evaluation)."""
         B = len(xs)
         vols, ptrs = _volumes(xs, U0s, p.C)
         x0, v0, r1, r2, G, P = _streams(streams)
@@ -414,10 +414,11 @@ class Context:
         bf = np.empty(B)
         fh = np.empty((B, G, P))
         ph = np.empty((B, G, P, 2))
+        ih = np.empty((B, G, P), np.int32)
         self._check(self.lib.pifcm_pso(self.h, vols, B, ct.byref(p.c()), P, G, _dp(x0), _dp(v0),
                                        _dp(r1), _dp(r2), float(w), float(c1), float(c2), _fp(c0),
-                                       ptrs, int(mode), _dp(bp), _dp(bf), _dp(fh), _dp(ph)))
-        return dict(best_pos=bp, best_fit=bf, fit_hist=fh, pos_hist=ph)
+                                       ptrs, int(mode), _dp(bp), _dp(bf), _dp(fh), _dp(ph), _ip(ih)))
+        return dict(best_pos=bp, best_fit=bf, fit_hist=fh, pos_hist=ph, iters_hist=ih)
 
     def pifcm_pso_interleaved(self, xs, p: Params, streams, centres0, U0s, steps=1, w=0.7, c1=1.5,
                               c2=1.5, mode=PIFCM_SWARM_BATCHED):

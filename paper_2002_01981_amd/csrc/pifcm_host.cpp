@@ -1690,11 +1690,17 @@ pifcm_status pifcm_pso(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, cons
                        int32_t P, int32_t G, const double* x0, const double* v0, const double* r1,
                        const double* r2, double w, double c1, double c2, const float* centres0,
                        const float* const* U0, int32_t mode, double* best_pos, double* best_fit,
-                       double* fit_hist, double* pos_hist) {
+                       double* fit_hist, double* pos_hist, int32_t* iters_hist) {
   if (!ctx) return PIFCM_E_INVALID;
   ctx->err.clear();
-  auto eval = [&](int, const float* parts, double* fit) -> pifcm_status {
-    return swarm_evaluate(ctx, vols, B, p, parts, P, centres0, U0, fit, nullptr, nullptr, mode);
+  std::vector<int32_t> its(iters_hist && B > 0 && P > 0 ? (size_t)B * P : 0);
+  auto eval = [&](int g, const float* parts, double* fit) -> pifcm_status {
+    TRY(swarm_evaluate(ctx, vols, B, p, parts, P, centres0, U0, fit, nullptr,
+                       iters_hist ? its.data() : nullptr, mode));
+    if (iters_hist)
+      for (int b = 0; b < B; ++b)
+        for (int q = 0; q < P; ++q) iters_hist[((size_t)b * G + g) * P + q] = its[(size_t)b * P + q];
+    return PIFCM_OK;
   };
   return pso_run(ctx, B, P, G, x0, v0, r1, r2, w, c1, c2, eval, best_pos, best_fit, fit_hist,
                  pos_hist, nullptr);
