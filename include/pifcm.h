@@ -116,6 +116,29 @@ pifcm_status ifcm_solve(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_par
                         float* U_out, float* centres_out, uint8_t* labels_out, double* J_out,
                         int32_t* iters_out, double* J_hist_out);
 
+/* ifcm_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture elsewhere in the program, serving loops, harnesses that
+ * forbid hipMalloc): the same solve, the same kernels, the same arguments,
+ * outputs and decomposition -- results are bit-identical to ifcm_solve's on
+ * the same context -- but no hipMalloc, hipFree or other allocating call.
+ * Its workspace (g_inv, the second membership buffer, tile sums, solve
+ * state, objective history; about 4 * (C + 1) bytes per voxel) lives in a
+ * device array of 256 MiB that the library holds on every GPU it runs on
+ * until the process ends; a C = 4 volume of up to about 13 million voxels
+ * fits.  A solve that needs more fails with PIFCM_E_INVALID (naming the
+ * bytes needed) before any work is queued; V > 1 is PIFCM_E_UNSUPPORTED.
+ * The array is shared by every call on that GPU and keeps the last call's
+ * contents (each call initialises what it reads): calls on one device are
+ * serialised inside the library, and every call finishes its work before
+ * it returns.  The call synchronises the context's stream, so it cannot
+ * itself be captured into a graph.  Unlike the other entry points,
+ * J_hist_out is copied straight into the caller's array and may hold
+ * partial values if a HIP error ends the call. */
+pifcm_status ifcm_solve_noalloc(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
+                                float lambda, float xi, const float* centres_in, const float* U_in,
+                                float* U_out, float* centres_out, uint8_t* labels_out, double* J_out,
+                                int32_t* iters_out, double* J_hist_out);
+
 /* Slab mode of ifcm_solve -- Algorithm 1 step 1 segments one slice z of the
  * volume with its 3D neighbours: only the planes [zbeg, zend) (e.g. [z,
  * z + 1)) are iterated; the memberships of every other plane stay those of

@@ -98,6 +98,8 @@ def load_library(path=LIB_PATH):
     lib.ifcm_solve.argtypes = [vp, P(_Volume), P(_Params), f32, f32, P(f32), vp, vp, P(f32), vp,
                                P(f64), P(i32), P(f64)]
     lib.ifcm_solve.restype = st
+    lib.ifcm_solve_noalloc.argtypes = lib.ifcm_solve.argtypes
+    lib.ifcm_solve_noalloc.restype = st
     lib.ifcm_solve_slab.argtypes = [vp, P(_Volume), i32, i32, P(_Params), f32, f32, P(f32), vp, vp,
                                     P(f32), vp, P(f64), P(i32), P(f64)]
     lib.ifcm_solve_slab.restype = st
@@ -274,6 +276,17 @@ class Context:
 
     def ifcm_solve(self, x, p: Params, lam, xi, centres, U_in=None, labels=False,
                    want_hist=False, U_out=None):
+        return self._solve("ifcm_solve", x, p, lam, xi, centres, U_in, labels, want_hist, U_out)
+
+    def ifcm_solve_noalloc(self, x, p: Params, lam, xi, centres, U_in=None, labels=False,
+                           want_hist=False, U_out=None):
+        """ifcm_solve in the library's per-device scratch (no device
+        allocation by the library; U_out and labels are allocated here unless
+        given)."""
+        return self._solve("ifcm_solve_noalloc", x, p, lam, xi, centres, U_in, labels,
+                           want_hist, U_out)
+
+    def _solve(self, name, x, p: Params, lam, xi, centres, U_in, labels, want_hist, U_out):
         import torch
         vol = _volume(x)
         c = _host_vec(centres, p.C, np.float32, "centres")
@@ -287,7 +300,7 @@ class Context:
         J = np.zeros(1, np.float64)
         it = np.zeros(1, np.int32)
         hist = np.zeros(max(1, p.max_iter), np.float64)
-        self._check(self.lib.ifcm_solve(
+        self._check(getattr(self.lib, name)(
             self.h, ct.byref(vol), ct.byref(p.c()), float(lam), float(xi), _fp(c),
             None if U_in is None else U_in.data_ptr(), U_out.data_ptr(), _fp(cout),
             None if lab is None else lab.data_ptr(), _dp(J), _ip(it),

@@ -28,7 +28,7 @@ HIPFLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 SOURCES = ["gather_c4.hip", "gather_c2_6.hip", "gather_c7_10.hip", "gather_c11_13.hip",
-           "gather_c14_16.hip", "pointwise.hip", "ring.hip", "ring2.hip", "adjoint.hip", "pifcm_host.cpp"]
+           "gather_c14_16.hip", "pointwise.hip", "ring.hip", "ring2.hip", "adjoint.hip", "scratch.hip", "pifcm_host.cpp"]
 
 
 def _hipcc():

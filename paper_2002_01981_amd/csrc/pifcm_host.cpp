@@ -591,6 +591,10 @@ pifcm_status pifcm_create(int device, void* hip_stream, pifcm_ctx** out) {
   }
   ensure(ctx, ctx->tvol, sizeof(VolDev) * kMaxBatchVols, "volume table");
   ensure(ctx, ctx->tpair, sizeof(PairDev) * kMaxPairs, "pair table");
+  // The device address of the no-allocation scratch, once per device (a
+  // failure here is reported by ifcm_solve_noalloc, which asks again).
+  void* sp = nullptr;
+  if (scratch_region(device, &sp) != hipSuccess) (void)hipGetLastError();
   *out = ctx;
   return PIFCM_OK;
 }
@@ -896,6 +900,66 @@ pifcm_status ifcm_solve(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_par
   if (J_out) *J_out = J;
   if (iters_out) *iters_out = T;
   if (J_hist_out) std::memcpy(J_hist_out, jh.data(), sizeof(double) * (size_t)T);
+  return PIFCM_OK;
+}
+
+pifcm_status ifcm_solve_noalloc(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_params* p,
+                                float lambda, float xi, const float* centres_in, const float* U_in,
+                                float* U_out, float* centres_out, uint8_t* labels_out, double* J_out,
+                                int32_t* iters_out, double* J_hist_out) {
+  if (!ctx) return PIFCM_E_INVALID;
+  ctx->err.clear();
+  TRY(check_solve_args(ctx, vol, p, lambda, xi, centres_in, U_in, U_out));
+  if (ring_params(p))
+    return fail(ctx, PIFCM_E_UNSUPPORTED, "ifcm_solve_noalloc covers the 3x3x3 neighbourhood (V = 1) only");
+  // The workspace of solve_run, carved out of this device's scratch array.
+  const int C = p->C;
+  const size_t N = nvox(*vol);
+  const size_t Np = (N + 63) / 64 * 64;
+  const int slots = solve_slots(ctx, vol, p, 0, vol->nz);
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t o_invg = 0;
+  const size_t o_ubuf = o_invg + al(Np * sizeof(float));
+  const size_t o_part = o_ubuf + al(N * C * sizeof(float));
+  const size_t o_st = o_part + al((size_t)slots * (2 * C + 1) * sizeof(float));
+  const size_t o_pair = o_st + al(sizeof(SolveState));
+  const size_t o_vol = o_pair + al(sizeof(PairDev));
+  const size_t o_jh = o_vol + al(sizeof(VolDev));
+  const size_t o_flags = o_jh + al((size_t)std::max(1, p->max_iter) * sizeof(double));
+  const size_t need = o_flags + al(2 * sizeof(int));
+  if (need > kScratchBytes)
+    return fail(ctx, PIFCM_E_INVALID,
+                "ifcm_solve_noalloc: this solve needs %zu bytes of scratch (N = %zu, C = %d, max_iter = %d), "
+                "more than the %zu bytes the library holds per device; use ifcm_solve",
+                need, N, C, p->max_iter, kScratchBytes);
+  std::mutex* mu = scratch_call_lock(ctx->device);
+  if (!mu) return fail(ctx, PIFCM_E_UNSUPPORTED, "device %d is beyond the scratch table", ctx->device);
+  std::lock_guard<std::mutex> lock(*mu);
+  TRY(begin(ctx));
+  void* base = nullptr;
+  HIPCHK(scratch_region(ctx->device, &base));
+  char* sc = (char*)base;
+  SolveWs ws;
+  ws.invg = (float*)(sc + o_invg);
+  ws.ubuf = (float*)(sc + o_ubuf);
+  ws.partials = (float*)(sc + o_part);
+  ws.st = (SolveState*)(sc + o_st);
+  ws.tpair = (PairDev*)(sc + o_pair);
+  ws.tvol = (VolDev*)(sc + o_vol);
+  ws.jhist = (double*)(sc + o_jh);
+  ws.flags = (int*)(sc + o_flags);
+  alignas(256) char stage[kStageBytes];  // pageable host staging
+  ws.stage = stage;
+  ws.jh_stage = nullptr;                  // the J history goes straight to J_hist_out
+  float c_tmp[kMaxC];
+  double J = 0.0;
+  int32_t T = 0;
+  TRY(solve_run(ctx, ws, vol, p, lambda, xi, centres_in, U_in, U_out, c_tmp, labels_out, &J, &T,
+                J_hist_out, 0, vol->nz));
+  TRY(finish(ctx));
+  if (centres_out) std::memcpy(centres_out, c_tmp, sizeof(float) * C);
+  if (J_out) *J_out = J;
+  if (iters_out) *iters_out = T;
   return PIFCM_OK;
 }
 

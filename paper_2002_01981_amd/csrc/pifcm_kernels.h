@@ -1,11 +1,20 @@
 // pifcm_kernels.h -- launchers of the HIP kernels (internal to libpifcm).
 #pragma once
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "pifcm_device.h"
 
 namespace pifcm {
+
+// Device scratch of the entry point that allocates nothing (scratch.hip):
+// kScratchBytes per device.  scratch_region gives this device's address of
+// the array (taken once per device, with that device current);
+// scratch_call_lock serialises the calls that use it on one device.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+hipError_t scratch_region(int device, void** ptr);
+std::mutex* scratch_call_lock(int device);
 
 // Fused IFCM step (step = true) or objective-only pass (step = false) over
 // the tiles of a launch; ty = waves per work group (1, 2 or 4; 4 unless

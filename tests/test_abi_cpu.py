@@ -116,6 +116,8 @@ def test_binding_rejects_bad_buffers_before_the_library(bare_ctx):
         lambda: bare_ctx.ifcm_solve(x, p, 0.1, 0.2, c, U_out=_u(n + 1)),
         lambda: bare_ctx.ifcm_solve(x, p, 0.1, 0.2, c[:3]),
         lambda: bare_ctx.ifcm_solve(x, p, 0.1, 0.2, c, U_in=_u(n).t()),
+        lambda: bare_ctx.ifcm_solve_noalloc(x, p, 0.1, 0.2, c, U_in=_u(n - 1)),
+        lambda: bare_ctx.ifcm_solve_noalloc(x, p, 0.1, 0.2, c, U_out=_u(n + 1)),
         lambda: bare_ctx.ifcm_solve_slab(x, 0, 1, p, 0.1, 0.2, c, _u(2 * n)),
         lambda: bare_ctx.swarm_evaluate([x, x], p, np.zeros((3, 2)), np.zeros((2, 4)), [_u(n)]),
         lambda: bare_ctx.swarm_evaluate([x, x], p, np.zeros((3, 5, 2)), np.zeros((2, 4)),
