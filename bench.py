@@ -388,7 +388,7 @@ def main():
         tuned_diff = float(np.max(np.abs(outd["fitness"] / out["fitness"] - 1.0)))
         ctx.close()
         ctx = ctx_b
-        plain = dict(decomposition="default (4 waves x 32 planes, 1 particle per item)",
+        plain = dict(decomposition="default (4 waves, each volume's default tile depth, 1 particle per item)",
                      ms_per_step=round(pl_ms, 3), value=work / (pl_ms * 1e-3),
                      launches_per_step=int(pl), avg_launch_us=round(pk_ms / max(pl, 1) * 1e3, 2),
                      batched_ms_per_step=round(bd_ms, 3),

@@ -221,8 +221,11 @@ pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B,
 
 /* Set the work decomposition of the fused step for these volumes by hand
  * (what pifcm_tune would otherwise choose): waves per work group (1, 2 or 4),
- * planes per tile (>= 1; clamped to the volume and to the 32-bit offset
- * range) and particles per work item (1 or 2; used by batched swarm
+ * planes per tile (>= 1, clamped to the volume and to the 32-bit offset
+ * range; 0 = the default depth: of the depths ceil(nz / k) and 32 that
+ * are at least min(nz, 32), the one with the fewest rounds of one pair's
+ * tiles on the resident waves times (depth + 4), as a solve without a chosen
+ * decomposition uses) and particles per work item (1 or 2; used by batched swarm
  * launches of P >= 2 particles).  Other values than 4 waves and 1 particle
  * are built for C = 4 only (PIFCM_E_UNSUPPORTED otherwise).  Kept in ctx for
  * these (C, m == 2, shape) keys, as a tuned choice is.  Results of every

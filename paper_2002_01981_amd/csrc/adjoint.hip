@@ -130,8 +130,10 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
     float* const sc = &s_c[wave][0][0];
 
 
-    // Prefetch registers of one plane: own cell (x, g_inv, U) and halo cell.
-    float rx, rg, ru[C], hxv, hu[C];
+    // Prefetch registers of one plane: own cell (x, g_inv, U, and in the
+    // iteration pass dJ/dU^(t+1), which only the voxel itself reads, three
+    // planes later) and halo cell.
+    float rx, rg, ru[C], rgn[C], hxv, hu[C];
     auto load_plane = [&](int q) __attribute__((always_inline)) {
       const bool pv = q >= 0 && q < nz;
       if (pv && active) {
@@ -139,11 +141,12 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
         rx = a.x[i];
         rg = a.invg[i];
         load_row<C>(as_global(a.U) + i * C, ru);
+        if constexpr (!EVAL) load_row<C>(as_global(a.Ubar_next) + i * C, rgn);
       } else {
         rx = 0.f;
         rg = 1.f;
 #pragma unroll
-        for (int j = 0; j < C; ++j) ru[j] = 0.f;
+        for (int j = 0; j < C; ++j) ru[j] = rgn[j] = 0.f;
       }
       if (pv && hvalid) {
         const size_t i = (size_t)q * psz + halo_xy;
@@ -169,13 +172,13 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
     };
 
     // Slots of the voxels p-1, p, p+1 of the lane's column: H and F
-    // numerators and the stored g_inv.
-    float hn[3][C], fn[3][C], gs[3];
+    // numerators, the stored g_inv and (iteration pass) dJ/dU^(t+1).
+    float hn[3][C], fn[3][C], gs[3], gns[3][C];
 #pragma unroll
     for (int s2 = 0; s2 < 3; ++s2) {
       gs[s2] = 1.f;
 #pragma unroll
-      for (int j = 0; j < C; ++j) hn[s2][j] = fn[s2][j] = 0.f;
+      for (int j = 0; j < C; ++j) hn[s2][j] = fn[s2][j] = gns[s2][j] = 0.f;
     }
 
     auto finalize = [&](int z, int S, int bz) __attribute__((always_inline)) {
@@ -230,12 +233,7 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
         const float is = 1.f / sw;
 #pragma unroll
         for (int j = 0; j < C; ++j) up[j] = w[j] * is;
-        float gin[C];
-        if (active) load_row<C>(as_global(a.Ubar_next) + i * C, gin);
-        else {
-#pragma unroll
-          for (int j = 0; j < C; ++j) gin[j] = 0.f;
-        }
+        const float* gin = gns[S];  // prefetched with the voxel's plane (0 outside)
         float dup[C];
         float t = 0.f;
 #pragma unroll
@@ -324,6 +322,8 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
       if (p + 1 <= zhi) {
         store_plane(bnext);
         gs[SC] = rg;
+#pragma unroll
+        for (int j = 0; j < C; ++j) gns[SC][j] = rgn[j];
         if (p + 2 <= zhi) load_plane(p + 2);
       }
       if (doA) finalize(p - 1, SA, bprev);
@@ -351,6 +351,8 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
           hn[1][j] = hn[2][j];
           fn[0][j] = fn[1][j];
           fn[1][j] = fn[2][j];
+          gns[0][j] = gns[1][j];
+          gns[1][j] = gns[2][j];
         }
         gs[0] = gs[1];
         gs[1] = gs[2];
@@ -421,12 +423,15 @@ __global__ __launch_bounds__(64 * adj_waves<C>()) void k_adj_transpose_tiled(con
 
     // Prefetch registers of one plane: own and halo cell (intensity as the
     // cell uses it in eq (5), its |g_inv| and q_inv, and da).
-    float rxc, rx, rgi, rqi, rd[C], hxc, hgi, hqi, hd[C];
+    // The own cell also brings the voxel's U (and in the objective pass its
+    // direct term), which only the voxel's own finalisation reads, three
+    // planes later.
+    float rxc, rx, rgi, rqi, rd[C], ru[C], rdir[C], hxc, hgi, hqi, hd[C];
     auto load_plane = [&](int q) __attribute__((always_inline)) {
       const bool pv = q >= 0 && q < nz;
       rx = rxc = rgi = rqi = hxc = hgi = hqi = 0.f;
 #pragma unroll
-      for (int j = 0; j < C; ++j) rd[j] = hd[j] = 0.f;
+      for (int j = 0; j < C; ++j) rd[j] = hd[j] = ru[j] = rdir[j] = 0.f;
       if (pv && active) {
         const size_t i = (size_t)q * psz + own_xy;
         rx = a.x[i];
@@ -435,6 +440,8 @@ __global__ __launch_bounds__(64 * adj_waves<C>()) void k_adj_transpose_tiled(con
         rgi = fabsf(g);
         rqi = adj_qinv(gx, gy, q, nx, ny, nz, wCa, wEb, wCb);
         load_row<C>(as_global(a.PQ) + i * C, rd);
+        load_row<C>(as_global(a.U) + i * C, ru);
+        if constexpr (EVAL) load_row<C>(as_global(a.Ubar_direct) + i * C, rdir);
       }
       if (pv && hvalid) {
         const size_t i = (size_t)q * psz + halo_xy;
@@ -468,25 +475,22 @@ __global__ __launch_bounds__(64 * adj_waves<C>()) void k_adj_transpose_tiled(con
 
     // Target slots (voxels p-1, p, p+1 of the lane's column): P-part and
     // class-weighted Q sums, and the target's own intensity.
-    float hP[3][C], fQ[3][C], xt[3];
+    float hP[3][C], fQ[3][C], xt[3], us[3][C], ds[3][C];
 #pragma unroll
     for (int s2 = 0; s2 < 3; ++s2) {
       xt[s2] = 0.f;
 #pragma unroll
-      for (int j = 0; j < C; ++j) hP[s2][j] = fQ[s2][j] = 0.f;
+      for (int j = 0; j < C; ++j) hP[s2][j] = fQ[s2][j] = us[s2][j] = ds[s2][j] = 0.f;
     }
     auto finalize = [&](int z, int S) __attribute__((always_inline)) {
       if (!active) return;
       const size_t k = (size_t)z * psz + own_xy;
-      float u[C], out[C];
-      load_row<C>(as_global(a.U) + k * C, u);
-      if constexpr (EVAL) load_row<C>(as_global(a.Ubar_direct) + k * C, out);
-      else {
+      float out[C];
 #pragma unroll
-        for (int j = 0; j < C; ++j) out[j] = 0.f;
+      for (int j = 0; j < C; ++j) {
+        const float t = hP[S][j] + 2.f * us[S][j] * fQ[S][j];
+        out[j] = EVAL ? ds[S][j] + t : t;
       }
-#pragma unroll
-      for (int j = 0; j < C; ++j) out[j] += hP[S][j] + 2.f * u[j] * fQ[S][j];
       store_row<C>(as_global(Ubar_out) + k * C, out);
     };
 
@@ -547,6 +551,11 @@ __global__ __launch_bounds__(64 * adj_waves<C>()) void k_adj_transpose_tiled(con
       if (p + 1 <= zhi) {
         store_plane(bnext);
         xt[SC] = rx;
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+          us[SC][j] = ru[j];
+          if constexpr (EVAL) ds[SC][j] = rdir[j];
+        }
         if (p + 2 <= zhi) load_plane(p + 2);
       }
       if (doA) finalize(p - 1, SA);
@@ -576,6 +585,10 @@ __global__ __launch_bounds__(64 * adj_waves<C>()) void k_adj_transpose_tiled(con
           hP[1][j] = hP[2][j];
           fQ[0][j] = fQ[1][j];
           fQ[1][j] = fQ[2][j];
+          us[0][j] = us[1][j];
+          us[1][j] = us[2][j];
+          ds[0][j] = ds[1][j];
+          ds[1][j] = ds[2][j];
         }
         xt[0] = xt[1];
         xt[1] = xt[2];

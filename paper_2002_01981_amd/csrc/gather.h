@@ -96,13 +96,13 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
   const float wCa = a.q2_sqdist ? 2.f : 4.f;
   const float wEb = a.q2_sqdist ? 2.f : 4.f, wCb = a.q2_sqdist ? 3.f : 9.f;
 
-  // Items: 8 contiguous ranges, one per XCD (work groups go to the XCDs
-  // round-robin), walked by that XCD's waves so neighbouring tiles share L2.
-  const int per = (a.nitems + 7) >> 3;
+  // Items: 8 contiguous ranges of about equal work, one per XCD (work groups
+  // go to the XCDs round-robin), walked by that XCD's waves so neighbouring
+  // tiles share L2.
   const int xcd = blockIdx.x & 7;
-  const int it_end = min(a.nitems, (xcd + 1) * per);
+  const int it_end = a.xcd_begin[xcd + 1];
   const int it_step = (gridDim.x >> 3) * NW;
-  for (int it = xcd * per + (blockIdx.x >> 3) * NW + wave; it < it_end; it += it_step) {
+  for (int it = a.xcd_begin[xcd] + (blockIdx.x >> 3) * NW + wave; it < it_end; it += it_step) {
     const int b = vol_of_item(a, it);
     const VolDev vd = ld_const(a.vols + b);
     const int r = it - a.item_begin[b];

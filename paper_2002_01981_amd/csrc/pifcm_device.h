@@ -81,6 +81,9 @@ struct LaunchArgs {
   float m;
   int32_t use_1d;      // items are 1D voxel blocks (pointwise kernels)
   int32_t item_begin[kMaxBatchVols + 1];  // first item of each volume
+  int32_t xcd_begin[9];  // items [xcd_begin[k], xcd_begin[k + 1]) go to the
+                         // work groups with blockIdx.x % 8 == k (one XCD):
+                         // contiguous ranges of about equal work
   const RingOff* ring; // general-neighbourhood offsets (ring kernel only)
   int32_t nring;       // number of offsets
   int32_t pad1;

@@ -38,7 +38,7 @@ struct GraphCache {
 
 struct TileShape {
   int nw = 4;   // wavefronts per work group of the fused step
-  int zc = 32;  // planes per tile
+  int zc = 0;   // planes per tile (0: the volume's default, default_zc)
   int pt = 1;   // particles per work item of the batched fused step (C = 4: 1 or 2)
 };
 
@@ -73,6 +73,7 @@ struct pifcm_ctx {
   double step_ms = 0.0;
   int64_t step_launches = 0;
   std::map<std::tuple<int, int, int, int, int>, TileShape> tuned;  // (C, m2, nx, ny, nz)
+  int occ_gather[kMaxC + 1][2] = {};  // resident work groups per CU of the fused step (4 waves)
   char arch[64] = "unknown";  // device architecture (tuning cache key)
 };
 
@@ -214,11 +215,47 @@ int max_zc(const pifcm_volume& v, int C) {
   return (int)std::max(0.0, std::min(z, (double)v.nz));
 }
 
+// Planes per tile when no shape was chosen for the volume.  A solve of one
+// pair runs ceil(tiles / R) rounds of tiles on the R waves the fused step
+// keeps resident (4 waves per work group), and a tile costs about zc + 4
+// plane passes (its two halo planes and the start of its walk): among the
+// depths ceil(nz / k) and 32 that are at least min(nz, 32) deep, take the
+// one with the fewest rounds * (zc + 4), the deeper one on a tie.  Batched
+// swarm launches hold many pairs and want deep tiles (fewer tile starts and
+// halo planes), hence the floor; the depth does not depend on the launch, so
+// every launch mode gives the same bits.  On the 181-plane brain volume this
+// is 46 planes (four tiles per column, one round) rather than 32 (six per
+// column, 1.3 rounds).
+int default_zc(pifcm_ctx* ctx, int C, bool m2, const pifcm_volume& v) {
+  int& occ = ctx->occ_gather[std::max(0, std::min(C, kMaxC))][m2 ? 1 : 0];
+  if (occ == 0) occ = std::max(1, gather_occupancy(C, 4, 1, m2, true));
+  const long R = (long)occ * ctx->num_cu * 4;
+  const long txy = (long)((v.nx + kWaveTileX - 1) / kWaveTileX) * ((v.ny + kWaveTileY - 1) / kWaveTileY);
+  const int floor_zc = std::min(v.nz, 32);
+  int best = v.nz;
+  long best_cost = -1;
+  auto consider = [&](int zc) {
+    const long tiles = txy * ((v.nz + zc - 1) / zc);
+    const long cost = (tiles + R - 1) / R * (zc + 4);
+    if (best_cost < 0 || cost < best_cost || (cost == best_cost && zc > best)) {
+      best_cost = cost;
+      best = zc;
+    }
+  };
+  for (int k = 1; k <= v.nz; ++k) {
+    const int zc = (v.nz + k - 1) / k;
+    if (zc < floor_zc) break;
+    consider(zc);
+  }
+  consider(floor_zc);
+  return best;
+}
+
 TileShape shape_for(pifcm_ctx* ctx, int C, bool m2, const pifcm_volume& v) {
   TileShape t;
   auto it = ctx->tuned.find(std::make_tuple(C, (int)m2, v.nx, v.ny, v.nz));
   if (it != ctx->tuned.end()) t = it->second;
-  else t.zc = std::min(v.nz, 32);
+  if (t.zc <= 0) t.zc = default_zc(ctx, C, m2, v);
   t.zc = std::max(1, std::min(t.zc, max_zc(v, C)));
   return t;
 }
@@ -414,14 +451,77 @@ pifcm_status prepare_ring(pifcm_ctx* ctx, const pifcm_params* p) {
 
 // One iteration (step) or the objective-only pass: the tile kernel, then the
 // per-pair finalise that adds the tile sums and advances the state.
+// A grid with a wave slot for every item of an even split by count (each XCD
+// runs its range in one pass) keeps that split: ranges balanced by work
+// would hand some XCD more items than it has waves.  A persistent grid,
+// whose waves walk several items each, takes the balanced ranges.
 hipError_t launch_step(int C, const LaunchArgs& a, int grid, int nw, bool m2, int kind, bool step,
                        hipStream_t s) {
-  hipError_t e = kind == kFcm     ? launch_fcm(C, a, grid, m2, step, s)
-                 : kind == kRing  ? launch_ring(C, a, grid, m2, step, s)
-                 : kind == kRing2 ? launch_ring2(C, a, grid, m2, step, s)
-                                  : launch_gather(C, a, grid, nw, m2, step, s);
+  LaunchArgs b = a;
+  const long per = ((long)a.nitems + 7) / 8;
+  if ((long)(grid / 8) * items_per_group(kind, nw) >= per)
+    for (int k = 0; k <= 8; ++k) b.xcd_begin[k] = (int32_t)std::min<long>(a.nitems, per * k);
+  hipError_t e = kind == kFcm     ? launch_fcm(C, b, grid, m2, step, s)
+                 : kind == kRing  ? launch_ring(C, b, grid, m2, step, s)
+                 : kind == kRing2 ? launch_ring2(C, b, grid, m2, step, s)
+                                  : launch_gather(C, b, grid, nw, m2, step, s);
   if (e != hipSuccess) return e;
-  return launch_finalize(C, a, a.nvol * a.P, step, s);
+  return launch_finalize(C, b, b.nvol * b.P, step, s);
+}
+
+// The 8 XCD ranges of a launch's items (LaunchArgs::xcd_begin): contiguous,
+// cut where the running work reaches k / 8 of the total.  A tile item's work
+// is the planes its tile walks plus 3 (the two halo planes and the start of
+// the walk); a pointwise item counts 1.  Items run volume by volume, particle
+// group by group, and within a group tile rows of equal depth follow each
+// other (tiles are numbered x, then y, then z), so the cuts are found per
+// volume and per tile row without visiting every item.  With volumes of
+// different depths in one launch an even split by count leaves some XCDs
+// with up to 15 % more work than the mean.
+void split_items(LaunchArgs& a, const VolDev* vh, int nvol) {
+  const int groups = (a.P + a.pt - 1) / a.pt;
+  auto depth = [&](const VolDev& v, int tz) { return std::min(v.zc, v.zend - v.zbeg - tz * v.zc); };
+  double total = 0.0;
+  for (int b = 0; b < nvol; ++b) {
+    const VolDev& v = vh[b];
+    double per_group = 0.0;
+    if (a.use_1d) per_group = v.tiles1d;
+    else
+      for (int tz = 0; tz < v.ntz; ++tz) per_group += (double)v.ntx * v.nty * (depth(v, tz) + 3);
+    total += per_group * groups;
+  }
+  a.xcd_begin[0] = 0;
+  int k = 1;
+  double cum = 0.0;
+  for (int b = 0; b < nvol && k < 8; ++b) {
+    const VolDev& v = vh[b];
+    const long txy = (long)v.ntx * v.nty;
+    const int nrow = a.use_1d ? 1 : v.ntz;  // runs of equal-cost items in a group
+    auto row_items = [&](int r) -> long { return a.use_1d ? (long)v.tiles1d : txy; };
+    auto row_cost = [&](int r) -> double { return a.use_1d ? 1.0 : (double)(depth(v, r) + 3); };
+    double per_group = 0.0;
+    for (int r = 0; r < nrow; ++r) per_group += row_items(r) * row_cost(r);
+    const double vol_end = cum + per_group * groups;
+    while (k < 8 && total * k / 8.0 < vol_end) {
+      const double target = total * k / 8.0;
+      const long g = std::min<long>(groups - 1, (long)((target - cum) / per_group));
+      double c = cum + per_group * g;
+      long item = a.item_begin[b] + g * (a.use_1d ? (long)v.tiles1d : (long)v.tiles);
+      for (int r = 0; r < nrow; ++r) {
+        const double rc = row_items(r) * row_cost(r);
+        if (c + rc >= target) {
+          item += std::min<long>(row_items(r), (long)std::ceil((target - c) / row_cost(r)));
+          break;
+        }
+        c += rc;
+        item += row_items(r);
+      }
+      a.xcd_begin[k++] = (int32_t)std::min<long>(item, a.nitems);
+    }
+    cum = vol_end;
+  }
+  while (k <= 8) a.xcd_begin[k++] = a.nitems;
+  for (int i = 1; i <= 8; ++i) a.xcd_begin[i] = std::max(a.xcd_begin[i], a.xcd_begin[i - 1]);
 }
 
 LaunchArgs make_args(const pifcm_ctx* ctx, const VolDev* vols_dev, const PairDev* pairs_dev,
@@ -452,6 +552,7 @@ LaunchArgs make_args(const pifcm_ctx* ctx, const VolDev* vols_dev, const PairDev
   }
   a.item_begin[nvol] = acc;
   a.nitems = acc;
+  split_items(a, vh, nvol);
   return a;
 }
 
@@ -520,7 +621,7 @@ bool tune_cache_get(const char* path, const std::string& key, TileShape& t, doub
     if (std::sscanf(e.second.c_str(), "{\"nw\": %d, \"zc\": %d, \"pt\": %d, \"step_ms\": %lf}", &nw, &zc, &pt,
                     &m) != 4)
       return false;
-    if ((nw != 1 && nw != 2 && nw != 4) || zc < 1 || (pt != 1 && pt != 2)) return false;
+    if ((nw != 1 && nw != 2 && nw != 4) || zc < 0 || (pt != 1 && pt != 2)) return false;
     t.nw = nw;
     t.zc = zc;
     t.pt = pt;
@@ -1465,7 +1566,7 @@ pifcm_status pifcm_set_decomposition(pifcm_ctx* ctx, const pifcm_volume* vols, i
   const int nw = waves_per_group, zc = planes_per_tile, pt = particles_per_item;
   if (nw != 1 && nw != 2 && nw != 4) return fail(ctx, PIFCM_E_INVALID, "waves_per_group = %d: 1, 2 or 4", nw);
   if (p->C != 4 && nw != 4) return fail(ctx, PIFCM_E_UNSUPPORTED, "waves_per_group = %d is built for C = 4 only", nw);
-  if (zc < 1) return fail(ctx, PIFCM_E_INVALID, "planes_per_tile = %d must be >= 1", zc);
+  if (zc < 0) return fail(ctx, PIFCM_E_INVALID, "planes_per_tile = %d must be >= 0 (0: the default)", zc);
   if (pt != 1 && pt != 2) return fail(ctx, PIFCM_E_INVALID, "particles_per_item = %d: 1 or 2", pt);
   if (p->C != 4 && pt != 1) return fail(ctx, PIFCM_E_UNSUPPORTED, "particles_per_item = 2 is built for C = 4 only");
   for (int b = 0; b < B; ++b)
@@ -1507,7 +1608,7 @@ pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
       apply(t);
       char desc[512];
       snprintf(desc, sizeof desc, "waves_per_group=%d planes_per_tile=%d particles_per_item=%d step_ms=%.4f cached [%s]",
-               t.nw, t.zc, t.pt, ms, key.c_str());
+               t.nw, shape_for(ctx, C, m2, vols[0]).zc, t.pt, ms, key.c_str());
       describe(desc);
       return PIFCM_OK;
     }
@@ -1562,16 +1663,20 @@ pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
   int maxz = 1;
   for (int b = 0; b < B; ++b) maxz = std::max(maxz, vols[b].nz);
   std::vector<TileShape> cands;
-  cands.push_back(TileShape{4, 32, 1});  // the default decomposition: the reference
+  // Candidate 0, the reference of the parity gate, is the default
+  // decomposition (4 waves, each volume's default depth, one particle per
+  // item); zc = 0 below stands for the default depth.
+  cands.push_back(TileShape{4, 0, 1});
   const int nws[3] = {1, 2, 4};
-  const int zcs[5] = {8, 16, 32, 64, 128};
+  const int zcs[6] = {0, 8, 16, 32, 64, 128};
   const int maxpt = (C == 4 && P >= 2) ? 2 : 1;
   for (int ptc = 1; ptc <= maxpt; ++ptc)
     for (int nw : nws) {
       if (C != 4 && nw != 4) continue;
       for (int zc : zcs) {
         if (zc / 2 >= maxz && zc != 8) continue;  // one candidate covers the whole column
-        if (nw == 4 && zc == 32 && ptc == 1) continue;
+        if (nw == 4 && zc == 0 && ptc == 1) continue;
+        if (zc == 0 && nw != 4) continue;
         cands.push_back(TileShape{nw, zc, ptc});
       }
     }
@@ -1647,7 +1752,10 @@ pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
       ok = ok && du <= 1e-4;
     }
     char one[64];
-    snprintf(one, sizeof one, "%s%dx%dx%d:%.3f%s", tried.empty() ? "" : " ", cands[ci].nw, cands[ci].zc,
+    char zs[16];
+    if (cands[ci].zc > 0) snprintf(zs, sizeof zs, "%d", cands[ci].zc);
+    else snprintf(zs, sizeof zs, "auto");
+    snprintf(one, sizeof one, "%s%dx%sx%d:%.3f%s", tried.empty() ? "" : " ", cands[ci].nw, zs,
              cands[ci].pt, ms, ok ? "" : "(differs)");
     tried += one;
     if (ok && ms < best_ms) {
@@ -1662,7 +1770,7 @@ pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
   char desc[1024];
   snprintf(desc, sizeof desc,
            "waves_per_group=%d planes_per_tile=%d particles_per_item=%d step_ms=%.4f candidates=%zu [%s]", best.nw,
-           best.zc, best.pt, best_ms, cands.size(), tried.c_str());
+           shape_for(ctx, C, m2, vols[0]).zc, best.pt, best_ms, cands.size(), tried.c_str());
   describe(desc);
   ctx->err.clear();
   return PIFCM_OK;

@@ -14,10 +14,9 @@ __global__ __launch_bounds__(256) void k_fcm_point(const LaunchArgs a) {
   constexpr int NT = 256;
   constexpr int NV = STEP ? 2 * C + 1 : 1;
   __shared__ float s_red[(NT / 64) * NV];
-  const int per = (a.nitems + 7) >> 3;
   const int xcd = blockIdx.x & 7;
-  const int it_end = min(a.nitems, (xcd + 1) * per);
-  for (int it = xcd * per + (blockIdx.x >> 3); it < it_end; it += gridDim.x >> 3) {
+  const int it_end = a.xcd_begin[xcd + 1];
+  for (int it = a.xcd_begin[xcd] + (blockIdx.x >> 3); it < it_end; it += gridDim.x >> 3) {
     const int b = vol_of_item(a, it);
     const VolDev vd = ld_const(a.vols + b);
     const int r = it - a.item_begin[b];

@@ -23,11 +23,10 @@ __global__ __launch_bounds__(64 * kRingWaves) void k_ifcm_ring(const LaunchArgs 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tx = lane & (TX - 1), ty = lane / TX;
-  const int per = (a.nitems + 7) >> 3;
   const int xcd = blockIdx.x & 7;
-  const int it_end = min(a.nitems, (xcd + 1) * per);
+  const int it_end = a.xcd_begin[xcd + 1];
   const int it_step = (gridDim.x >> 3) * kRingWaves;
-  for (int it = xcd * per + (blockIdx.x >> 3) * kRingWaves + wave; it < it_end; it += it_step) {
+  for (int it = a.xcd_begin[xcd] + (blockIdx.x >> 3) * kRingWaves + wave; it < it_end; it += it_step) {
     const int b = vol_of_item(a, it);
     const VolDev vd = ld_const(a.vols + b);
     const int r = it - a.item_begin[b];

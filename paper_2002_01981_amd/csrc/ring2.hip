@@ -135,11 +135,10 @@ __global__ __launch_bounds__(64 * kRing2Waves) void k_ifcm_ring2(const LaunchArg
   const float W1 = a.W[1], W2 = a.W[2];
   auto qw = [&](int s2) { return a.q2_sqdist ? (float)s2 : (float)(s2 * s2); };
 
-  const int per = (a.nitems + 7) >> 3;
   const int xcd = blockIdx.x & 7;
-  const int it_end = min(a.nitems, (xcd + 1) * per);
+  const int it_end = a.xcd_begin[xcd + 1];
   const int it_step = (gridDim.x >> 3) * NW;
-  for (int it = xcd * per + (blockIdx.x >> 3) * NW + wave; it < it_end; it += it_step) {
+  for (int it = a.xcd_begin[xcd] + (blockIdx.x >> 3) * NW + wave; it < it_end; it += it_step) {
     const int b = vol_of_item(a, it);
     const VolDev vd = ld_const(a.vols + b);
     const int r = it - a.item_begin[b];

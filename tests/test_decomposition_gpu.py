@@ -100,7 +100,7 @@ def test_decomposition_arguments(ctx):
     from paper_2002_01981_amd import PifcmError
     from paper_2002_01981_amd.abi import PIFCM_E_INVALID, PIFCM_E_UNSUPPORTED
     x = _volumes(ctx)[0][1]
-    for args, status in (((3, 32, 1), PIFCM_E_INVALID), ((4, 0, 1), PIFCM_E_INVALID),
+    for args, status in (((3, 32, 1), PIFCM_E_INVALID), ((4, -1, 1), PIFCM_E_INVALID),
                          ((4, 32, 3), PIFCM_E_INVALID)):
         with pytest.raises(PifcmError) as e:
             ctx.pifcm_set_decomposition([x], _P(C=4), *args)
@@ -108,3 +108,20 @@ def test_decomposition_arguments(ctx):
     with pytest.raises(PifcmError) as e:
         ctx.pifcm_set_decomposition([x], _P(C=3), 4, 32, 2)
     assert e.value.status == PIFCM_E_UNSUPPORTED
+
+
+def test_default_depth_by_hand_is_the_default(ctx):
+    """planes_per_tile = 0 sets the default depth: the same bits as a context
+    that never chose a decomposition."""
+    from paper_2002_01981_amd import Context
+    xo, xg, c0, U0 = _volumes(ctx)[1]
+    p = _P(C=4, m=2.0, eps=0.0, max_iter=6)
+    fresh = Context(0)
+    try:
+        a = fresh.ifcm_solve(xg, p, 0.3, 0.2, c0, U_in=U0, want_hist=True)
+    finally:
+        fresh.close()
+    ctx.pifcm_set_decomposition([xg], p, 4, 0, 1)
+    b = ctx.ifcm_solve(xg, p, 0.3, 0.2, c0, U_in=U0, want_hist=True)
+    assert np.array_equal(host(a["U"]), host(b["U"]))
+    assert np.array_equal(a["c"], b["c"]) and np.array_equal(a["J_hist"], b["J_hist"])

@@ -91,8 +91,9 @@ def test_normalize_in_place_and_constant(ctx):
                                    (2, 70, 20)])
 @pytest.mark.parametrize("lam,xi", [(0.3, 0.4), (0.0, 0.0), (0.9, 0.7)])
 def test_steps_span_tiles(ctx, shape, lam, xi):
-    """Wave tiles are 16 x 4 columns by up to 32 planes (default decomposition):
-    these shapes cover several tiles in every direction with ragged tails."""
+    """Wave tiles are 16 x 4 columns by 32 planes (the default depth of
+    these small volumes): these shapes cover several tiles in every
+    direction with ragged tails."""
     raw = synth.random_ellipsoids(shape=shape, seed=sum(shape), sigma=0.07)[0]
     g, o = _run_steps(ctx, raw, 4, lam, xi, steps=3, seed=shape[0])
     _assert_close(g, o, 4, lam, xi)

@@ -236,6 +236,15 @@ def test_fused_step_walk(nzs):
                 check(gather_walk, nz, zbeg, zend, zc, offset_planes=1)
 
 
+def test_fused_step_walk_every_depth():
+    """The default depth of a volume is some ceil(nz / k) (and
+    pifcm_set_decomposition takes any depth): every depth of a spread of
+    plane counts."""
+    for nz in list(range(1, 40)) + list(range(40, 320, 13)):
+        for zc in range(1, nz + 1):
+            check(gather_walk, nz, 0, nz, zc, offset_planes=1)
+
+
 @pytest.mark.parametrize("nzs", NZ_CHUNKS, ids=lambda r: f"nz{r.start}-{r.stop - 1}")
 def test_two_ring_walk(nzs):
     for nz in nzs:
