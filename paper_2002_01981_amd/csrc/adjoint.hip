@@ -45,10 +45,32 @@ constexpr int kAdjPW = 4;                    // waves per work group of k_adj_po
 // Inverse of the denominator of eq (7) for voxel (gx, gy, gz): the weights of
 // its in-volume neighbours summed from its position (in-plane edges weigh 1,
 // in-plane corners wCa; per existing off-plane the centre 1, edges wEb,
-// corners wCb).  Both adjoint kernels form it with this one function, so the
-// transpose rebuilds Q bit for bit.
-__device__ __forceinline__ float adj_qinv(int gx, int gy, int gz, int nx, int ny, int nz, float wCa,
-                                          float wEb, float wCb) {
+// corners wCb).  The per-voxel kernel forms the three values of its column
+// (by the number of existing off-planes: 0, 1, 2) once per tile and picks
+// one per plane (adj_qinv_column, adj_qinv_at); the transpose, which needs
+// them for its halo cells too, forms each cell's one value as it stages it
+// (adj_qinv_cell; measured faster there than carrying six values).  The
+// expressions are the same, so the transpose rebuilds Q bit for bit.
+struct AdjQinv {
+  float v[3];
+};
+__device__ __forceinline__ AdjQinv adj_qinv_column(int gx, int gy, int nx, int ny, float wCa, float wEb,
+                                                   float wCb) {
+  const int ex = (gx > 0) + (gx < nx - 1), ey = (gy > 0) + (gy < ny - 1);
+  const float e = (float)(ex + ey), co = (float)(ex * ey);
+  const float q0 = e + wCa * co, q1 = 1.f + wEb * e + wCb * co;
+  AdjQinv r;
+  r.v[0] = q0 > 0.f ? 1.f / q0 : 0.f;
+  r.v[1] = 1.f / (q0 + q1);
+  r.v[2] = 1.f / (q0 + 2.f * q1);
+  return r;
+}
+__device__ __forceinline__ float adj_qinv_at(const AdjQinv& q, int gz, int nz) {
+  const int np = (gz > 0) + (gz < nz - 1);
+  return np == 2 ? q.v[2] : (np == 1 ? q.v[1] : q.v[0]);
+}
+__device__ __forceinline__ float adj_qinv_cell(int gx, int gy, int gz, int nx, int ny, int nz, float wCa,
+                                               float wEb, float wCb) {
   const int ex = (gx > 0) + (gx < nx - 1), ey = (gy > 0) + (gy < ny - 1);
   const float e = (float)(ex + ey), co = (float)(ex * ey);
   const float q0 = e + wCa * co, q1 = 1.f + wEb * e + wCb * co;
@@ -128,7 +150,7 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
     const size_t own_xy = active ? (size_t)gy * nx + gx : 0;
     const size_t halo_xy = hvalid ? (size_t)hy * nx + hx : 0;
     float* const sc = &s_c[wave][0][0];
-
+    const AdjQinv qcol = adj_qinv_column(gx, gy, nx, ny, wCa, wEb, wCb);
 
     // Prefetch registers of one plane: own cell (x, g_inv, U, and in the
     // iteration pass dJ/dU^(t+1), which only the voxel itself reads, three
@@ -171,8 +193,11 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
       return sc + (buf * kAdjCells + own_cell + dy * kAdjHX + dx) * CW;
     };
 
-    // Slots of the voxels p-1, p, p+1 of the lane's column: H and F
-    // numerators, the stored g_inv and (iteration pass) dJ/dU^(t+1).
+    // Slots of the voxels p-1, p, p+1 of the lane's column: H numerators of
+    // the first C - 1 clusters (the last H is 1 minus their sum, as in the
+    // forward step), F numerators, the stored g_inv and (iteration pass)
+    // dJ/dU^(t+1).
+    constexpr int CH = C - 1;
     float hn[3][C], fn[3][C], gs[3], gns[3][C];
 #pragma unroll
     for (int s2 = 0; s2 < 3; ++s2) {
@@ -185,11 +210,17 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
       const float* own = cell_at(bz, 0, 0);
       const float xv = own[0];
       const float gi = fabsf(gs[S]);
-      const float iq = adj_qinv(gx, gy, z, nx, ny, nz, wCa, wEb, wCb);
+      const float iq = adj_qinv_at(qcol, z, nz);
       float H[C], F[C], av[C], dd[C], e[C], d[C];
+      float sh = 0.f;
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        H[j] = hn[S][j] * gi;
+        sh += H[j];
+      }
+      H[CH] = gi != 0.f ? 1.f - sh : 0.f;  // sum_j H_ij = 1 (0 without neighbours)
 #pragma unroll
       for (int j = 0; j < C; ++j) {
-        H[j] = hn[S][j] * gi;
         F[j] = fn[S][j] * iq;
         av[j] = 1.f - a.lam * H[j] - a.xi * F[j];
         dd[j] = xv - cj[j];
@@ -213,9 +244,11 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
         float w[C], up[C];
         float sw = 0.f;
         if constexpr (M2) {
+          // Hardware reciprocals (about 1 ulp): these recomputed forward
+          // values only feed the derivative.
 #pragma unroll
           for (int j = 0; j < C; ++j) {
-            w[j] = 1.f / d[j];
+            w[j] = __builtin_amdgcn_rcpf(d[j]);
             sw += w[j];
           }
         } else {
@@ -230,7 +263,7 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
             sw += w[j];
           }
         }
-        const float is = 1.f / sw;
+        const float is = M2 ? __builtin_amdgcn_rcpf(sw) : 1.f / sw;
 #pragma unroll
         for (int j = 0; j < C; ++j) up[j] = w[j] * is;
         const float* gin = gns[S];  // prefetched with the voxel's plane (0 outside)
@@ -245,7 +278,8 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
 #pragma unroll
         for (int j = 0; j < C; ++j) {
           const float dw = (dup[j] - t) * is;
-          dbar[j] = -dw * w[j] / ((m - 1.f) * d[j]);
+          // m = 2: w_j = 1 / d_j, so w_j / ((m - 1) d_j) = w_j^2
+          dbar[j] = M2 ? -dw * w[j] * w[j] : -dw * w[j] / ((m - 1.f) * d[j]);
         }
       }
       // da is the transpose's source: P = -lambda da g_inv, Q = -xi da q_inv
@@ -297,14 +331,14 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
             }
             const float gA = fabsf(xcA - xk), gC = fabsf(xC - xk);  // eq (6)
 #pragma unroll
-            for (int j = 0; j < C; ++j) {
+            for (int j = 0; j < CH; ++j) {
               hn[SA][j] = fmaf(u[j], gA, hn[SA][j]);
               hC[j] = fmaf(u[j], gC, hC[j]);
             }
             if (n != 0) {
               const float gB = fabsf(xcB - xk);
 #pragma unroll
-              for (int j = 0; j < C; ++j) hn[SB][j] = fmaf(u[j], gB, hn[SB][j]);
+              for (int j = 0; j < CH; ++j) hn[SB][j] = fmaf(u[j], gB, hn[SB][j]);
             }
           }
         }
@@ -381,8 +415,11 @@ template <int C, bool EVAL>
 __global__ __launch_bounds__(64 * adj_waves<C>()) void k_adj_transpose_tiled(const AdjArgs a, float* Ubar_out) {
   constexpr int kAdjWaves = adj_waves<C>();
   constexpr int CP = (C + 3) / 4 * 4;
-  constexpr int CW = 4 + 2 * CP;             // floats per staged cell: xc (+3 pad), P, Q
+  constexpr int CW = 2 * CP;                 // floats per staged cell: P, Q
+  // P and Q per cell, the cell's xc in an array of its own (no padding of
+  // the float4 rows): three work groups of four waves fit a CU's LDS.
   __shared__ __align__(16) float s_c[kAdjWaves][3][kAdjCells * CW];
+  __shared__ float s_xc[kAdjWaves][3][kAdjCells];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tx = lane & (kAdjTX - 1), ty = lane / kAdjTX;
@@ -438,7 +475,7 @@ __global__ __launch_bounds__(64 * adj_waves<C>()) void k_adj_transpose_tiled(con
         const float g = a.invg[i];
         rxc = g < 0.f ? rx - 1.f : rx;
         rgi = fabsf(g);
-        rqi = adj_qinv(gx, gy, q, nx, ny, nz, wCa, wEb, wCb);
+        rqi = adj_qinv_cell(gx, gy, q, nx, ny, nz, wCa, wEb, wCb);
         load_row<C>(as_global(a.PQ) + i * C, rd);
         load_row<C>(as_global(a.U) + i * C, ru);
         if constexpr (EVAL) load_row<C>(as_global(a.Ubar_direct) + i * C, rdir);
@@ -449,28 +486,30 @@ __global__ __launch_bounds__(64 * adj_waves<C>()) void k_adj_transpose_tiled(con
         const float g = a.invg[i];
         hxc = g < 0.f ? xh - 1.f : xh;
         hgi = fabsf(g);
-        hqi = adj_qinv(hx, hy, q, nx, ny, nz, wCa, wEb, wCb);
+        hqi = adj_qinv_cell(hx, hy, q, nx, ny, nz, wCa, wEb, wCb);
         load_row<C>(as_global(a.PQ) + i * C, hd);
       }
     };
     // P = -lambda da g_inv and Q = -xi da q_inv of the cell (the products the
     // per-voxel kernel would have formed).
-    auto store_cell = [&](float* cell, float xc, float gi, float qi, const float (&dav)[C])
+    auto store_cell = [&](float* cell, float* xcell, float xc, float gi, float qi, const float (&dav)[C])
         __attribute__((always_inline)) {
-      cell[0] = xc;
+      *xcell = xc;
       float P[C], Q[C];
 #pragma unroll
       for (int j = 0; j < C; ++j) {
         P[j] = -a.lam * dav[j] * gi;
         Q[j] = -a.xi * dav[j] * qi;
       }
-      lds_cell_store<C, CP>(cell + 4, P);  // offset 4 keeps the float4s aligned
-      lds_cell_store<C, CP>(cell + 4 + CP, Q);
+      lds_cell_store<C, CP>(cell, P);
+      lds_cell_store<C, CP>(cell + CP, Q);
     };
+    float* const sxw = &s_xc[wave][0][0];
     auto store_plane = [&](int buf) __attribute__((always_inline)) {
       float* base = sc + buf * kAdjCells * CW;
-      store_cell(base + own_cell * CW, rxc, rgi, rqi, rd);
-      if (hlane) store_cell(base + halo_cell * CW, hxc, hgi, hqi, hd);
+      float* xb = sxw + buf * kAdjCells;
+      store_cell(base + own_cell * CW, xb + own_cell, rxc, rgi, rqi, rd);
+      if (hlane) store_cell(base + halo_cell * CW, xb + halo_cell, hxc, hgi, hqi, hd);
     };
 
     // Target slots (voxels p-1, p, p+1 of the lane's column): P-part and
@@ -513,10 +552,10 @@ __global__ __launch_bounds__(64 * adj_waves<C>()) void k_adj_transpose_tiled(con
 #pragma unroll
           for (int dx = -1; dx <= 1; ++dx) {
             const float* cell = cell_at(bp, dy, dx);
-            const float xc = cell[0];
+            const float xc = sxw[bp * kAdjCells + own_cell + dy * kAdjHX + dx];
             float P[C], Q[C];
-            lds_cell_load<C, CP>(cell + 4, P);
-            lds_cell_load<C, CP>(cell + 4 + CP, Q);
+            lds_cell_load<C, CP>(cell, P);
+            lds_cell_load<C, CP>(cell + CP, Q);
             const int n = (dx != 0) + (dy != 0);
 #pragma unroll
             for (int j = 0; j < C; ++j) {
