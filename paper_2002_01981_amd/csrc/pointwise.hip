@@ -207,24 +207,49 @@ __global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ raw, s
                                                 uint32_t* __restrict__ mm, int* __restrict__ flag) {
   uint32_t lo = 0xffffffffu, hi = 0u;
   bool bad = false;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x) {
-    const float v = raw[i];
-    if (!isfinite(v)) bad = true;
+  auto take = [&](float v) {
+    bad = bad || !isfinite(v);
     const uint32_t k = fkey(v);
     lo = min(lo, k);
     hi = max(hi, k);
+  };
+  // Four independent loads in flight per thread, then the remainder.
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const float v0 = raw[i], v1 = raw[i + stride], v2 = raw[i + 2 * stride], v3 = raw[i + 3 * stride];
+    take(v0);
+    take(v1);
+    take(v2);
+    take(v3);
   }
+  for (; i < n; i += stride) take(raw[i]);
+  // Wave, then work group, then one atomic per work group and key (min and
+  // max of the keys do not depend on the order).
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
     lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
     hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
   }
+  __shared__ uint32_t s_lo[4], s_hi[4];
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
   if ((threadIdx.x & 63) == 0) {
+    s_lo[threadIdx.x >> 6] = lo;
+    s_hi[threadIdx.x >> 6] = hi;
+  }
+  if (bad) s_bad = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) {
+      lo = min(lo, s_lo[w]);
+      hi = max(hi, s_hi[w]);
+    }
     atomicMin(&mm[0], lo);
     atomicMax(&mm[1], hi);
+    if (s_bad) atomicOr(flag, 1);
   }
-  if (bad) atomicOr(flag, 1);
 }
 __global__ __launch_bounds__(256) void k_normalize(const float* raw, size_t n,
                                                    const uint32_t* __restrict__ mm, float* out) {
@@ -360,7 +385,8 @@ hipError_t launch_permute(const float* U, size_t N, int C, const int32_t* perm, 
 }
 
 hipError_t launch_minmax(const float* raw, size_t n, uint32_t* mm, int* flag, hipStream_t s) {
-  const int g = std::min(small_grid(n), 2048);
+  // 256 threads per work group (the reduction above assumes four waves)
+  const int g = std::min(small_grid(n), 1024);
   hipLaunchKernelGGL(k_minmax, dim3(g), dim3(256), 0, s, raw, n, mm, flag);
   return hipGetLastError();
 }
