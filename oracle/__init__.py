@@ -43,11 +43,15 @@ _lib = None
 
 
 def lib():
+    """The oracle library: oracle/liboracle.so (built on first use), or the
+    build that PIFCM_ORACLE_LIB names (the tests' mutation check loads
+    deliberately broken copies this way)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        path = os.environ.get("PIFCM_ORACLE_LIB", "") or LIB
+        if path == LIB and not os.path.exists(LIB):
             build()
-        _lib = ct.CDLL(LIB)
+        _lib = ct.CDLL(path)
         d, i, f = ct.POINTER(ct.c_double), ct.c_int, ct.POINTER(ct.c_float)
         pp = ct.POINTER(_Params)
         i64 = ct.c_int64

@@ -313,6 +313,37 @@ def test_pso_one_generation_by_hand(orc):
     assert out["best_fit"] == fits.min()
 
 
+def test_pso_personal_best_pull(orc):
+    """The personal-best term: with inertia 1, no global pull and c1 r1 = 2,
+    a particle moves by v0 in the first update; in the second it returns to
+    its start if that was no worse (pbest stays x0: x0 + 2 v0 - 2 v0 = x0),
+    and otherwise moves on by v0 again (pbest is the current position).
+    Starts and velocities are kept away from the box edges."""
+    x, p, c0, U0, st = _pso_case(orc, P=8, G=3, seed=11)
+    rng = np.random.default_rng(12)
+    x0 = 0.3 + 0.4 * rng.random((8, 2))
+    v0 = 0.05 * (2 * rng.random((8, 2)) - 1)
+    st = dict(x0=x0, v0=v0, r1=np.ones_like(st["r1"]), r2=np.zeros_like(st["r2"]))
+    out = orc.pso(x, c0, U0, p, st, w=1.0, c1=2.0, c2=0.0)
+    ph, fh = out["pos_hist"], out["fit_hist"]
+    np.testing.assert_allclose(ph[1], x0 + v0, rtol=0, atol=1e-15)
+    improved = fh[1] < fh[0]
+    expect = np.where(improved[:, None], x0 + 2 * v0, x0)
+    np.testing.assert_allclose(ph[2], expect, rtol=0, atol=1e-15)
+    assert improved.any() and not improved.all()
+
+
+def test_pso_global_best_pull(orc):
+    """The global-best term alone (w = c1 = 0, c2 r2 = 1) puts every particle
+    on the best position of the previous generations after each update."""
+    x, p, c0, U0, st = _pso_case(orc, P=6, G=3, seed=13)
+    st = dict(x0=st["x0"], v0=st["v0"], r1=np.zeros_like(st["r1"]), r2=np.ones_like(st["r2"]))
+    out = orc.pso(x, c0, U0, p, st, w=0.0, c1=0.0, c2=1.0)
+    ph, fh = out["pos_hist"], out["fit_hist"]
+    best = ph[0][int(np.argmin(fh[0]))]
+    np.testing.assert_allclose(ph[1], np.broadcast_to(best, ph[1].shape), rtol=0, atol=1e-15)
+
+
 def test_pso_best_is_reevaluated_fitness(orc):
     x, p, c0, U0, st = _pso_case(orc, P=6, G=4, seed=8)
     out = orc.pso(x, c0, U0, p, st)
