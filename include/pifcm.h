@@ -125,7 +125,7 @@ pifcm_status ifcm_solve(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_par
  * state, objective history; about 4 * (C + 1) bytes per voxel) lives in a
  * device array of 256 MiB that the library holds on every GPU it runs on
  * until the process ends; a C = 4 volume of up to about 13 million voxels
- * fits.  A solve that needs more fails with PIFCM_E_INVALID (naming the
+ * fits.  Its host staging is the pinned buffer pifcm_create allocates.  A solve that needs more fails with PIFCM_E_INVALID (naming the
  * bytes needed) before any work is queued; V > 1 is PIFCM_E_UNSUPPORTED.
  * The array is shared by every call on that GPU and keeps the last call's
  * contents (each call initialises what it reads): calls on one device are

@@ -43,6 +43,8 @@ struct TileShape {
 };
 
 constexpr int kChunk = 8;            // iterations between stop-flag reads
+// Host staging of one solve: its state, pair and volume records.
+constexpr size_t kStageBytes = (sizeof(SolveState) + sizeof(PairDev) + sizeof(VolDev) + 64 + 255) / 256 * 256;
 constexpr float kMaxWeight = 1000.f; // |lambda|, |xi| accepted
 constexpr int kMaxPairs = 65536;
 
@@ -693,9 +695,14 @@ pifcm_status pifcm_create(int device, void* hip_stream, pifcm_ctx** out) {
   ensure(ctx, ctx->tvol, sizeof(VolDev) * kMaxBatchVols, "volume table");
   ensure(ctx, ctx->tpair, sizeof(PairDev) * kMaxPairs, "pair table");
   // The device address of the no-allocation scratch, once per device (a
-  // failure here is reported by ifcm_solve_noalloc, which asks again).
+  // failure here is reported by ifcm_solve_noalloc, which asks again), and
+  // the pinned host staging that solve uses (it only ever grows).
   void* sp = nullptr;
   if (scratch_region(device, &sp) != hipSuccess) (void)hipGetLastError();
+  if (ensure_pinned(ctx, kStageBytes + 4096) != PIFCM_OK) {
+    pifcm_destroy(ctx);
+    return PIFCM_E_OOM;
+  }
   *out = ctx;
   return PIFCM_OK;
 }
@@ -830,7 +837,6 @@ struct SolveWs {
   double* jh_stage = nullptr;  // host [max_iter] staging of the J history, or NULL to copy
                                // it straight into the caller's array
 };
-constexpr size_t kStageBytes = (sizeof(SolveState) + sizeof(PairDev) + sizeof(VolDev) + 64 + 255) / 256 * 256;
 
 // Tile slots of a solve over planes [zbeg, zend) (the larger of the tiled and
 // pointwise decompositions).
@@ -1049,9 +1055,8 @@ pifcm_status ifcm_solve_noalloc(pifcm_ctx* ctx, const pifcm_volume* vol, const p
   ws.tvol = (VolDev*)(sc + o_vol);
   ws.jhist = (double*)(sc + o_jh);
   ws.flags = (int*)(sc + o_flags);
-  alignas(256) char stage[kStageBytes];  // pageable host staging
-  ws.stage = stage;
-  ws.jh_stage = nullptr;                  // the J history goes straight to J_hist_out
+  ws.stage = (char*)ctx->pinned;  // allocated at pifcm_create, at least kStageBytes
+  ws.jh_stage = nullptr;          // the J history goes straight to J_hist_out
   float c_tmp[kMaxC];
   double J = 0.0;
   int32_t T = 0;
