@@ -77,17 +77,21 @@ __global__ __launch_bounds__(256) void k_fcm_point(const LaunchArgs a) {
 // neighbours all have its intensity, -1 / (number of neighbours), which the
 // fused step turns into the equal-weight mean; 0 for a voxel without
 // neighbours.  Also flags non-finite intensities.
+// A work group covers 64 x 4 columns of the volume (the x-y tile of
+// blockIdx.x) and walks planes blockIdx.y, blockIdx.y + gridDim.y, ...: the
+// voxel position comes from the launch shape, not from dividing a flat
+// index.  The neighbours are read through the caches in a fixed order.
 __global__ __launch_bounds__(256) void k_invariants(const float* __restrict__ x, float* __restrict__ invg,
                                                     int nx, int ny, int nz, int* __restrict__ flag) {
-  const size_t N = (size_t)nx * ny * nz;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
-       i += (size_t)gridDim.x * blockDim.x) {
-    const int gx = (int)(i % nx);
-    const size_t r = i / nx;
-    const int gy = (int)(r % ny);
-    const int gz = (int)(r / ny);
+  const int ntx = (nx + 63) >> 6;
+  const int gx = (int)(blockIdx.x % ntx) * 64 + (int)(threadIdx.x & 63);
+  const int gy = (int)(blockIdx.x / ntx) * 4 + (int)(threadIdx.x >> 6);
+  if (gx >= nx || gy >= ny) return;
+  bool bad = false;
+  for (int gz = blockIdx.y; gz < nz; gz += gridDim.y) {
+    const size_t i = ((size_t)gz * ny + gy) * nx + gx;
     const float xi = x[i];
-    if (!isfinite(xi)) atomicOr(flag, 1);
+    bad = bad || !isfinite(xi);
     float gsum = 0.f;
     int cnt = 0;
     for (int dz = -1; dz <= 1; ++dz)
@@ -101,6 +105,7 @@ __global__ __launch_bounds__(256) void k_invariants(const float* __restrict__ x,
         }
     invg[i] = gsum > 0.f ? 1.f / gsum : (cnt > 0 ? -1.f / (float)cnt : 0.f);
   }
+  if (bad) atomicOr(flag, 1);
 }
 
 // U^(0) from centres (eq (2) with the attraction factor 1).
@@ -355,8 +360,11 @@ static int small_grid(size_t n) { return (int)std::max<size_t>(1, std::min<size_
 
 hipError_t launch_invariants(const float* x, float* invg, int nx, int ny, int nz, int* flag,
                              hipStream_t s) {
-  const size_t N = (size_t)nx * ny * nz;
-  hipLaunchKernelGGL(k_invariants, dim3(small_grid(N)), dim3(256), 0, s, x, invg, nx, ny, nz, flag);
+  const long tiles = (long)((nx + 63) / 64) * ((ny + 3) / 4);
+  if (tiles > 0x7fffffffL) return hipErrorInvalidValue;
+  const int planes = std::max(1, std::min(nz, 65535));
+  hipLaunchKernelGGL(k_invariants, dim3((unsigned)tiles, (unsigned)planes), dim3(256), 0, s, x, invg, nx, ny,
+                     nz, flag);
   return hipGetLastError();
 }
 
