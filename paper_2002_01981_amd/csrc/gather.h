@@ -97,12 +97,34 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
   const float wEb = a.q2_sqdist ? 2.f : 4.f, wCb = a.q2_sqdist ? 3.f : 9.f;
 
   // Items: 8 contiguous ranges of about equal work, one per XCD (work groups
-  // go to the XCDs round-robin), walked by that XCD's waves so neighbouring
-  // tiles share L2.
+  // go to the XCDs round-robin), walked in order by that XCD's waves, so
+  // neighbouring tiles run together and share L2.  When the range holds more
+  // items than the XCD has waves, each wave first takes its share of the
+  // first nine tenths by index (items w, w + W, w + 2W, ...), and the last
+  // tenth is handed out one item at a time to whichever wave is free (a
+  // counter per XCD): the tail of the launch stays balanced while the
+  // counter sees few requests (items whose particles have all stopped cost
+  // nothing, so handing every item out would make waves queue on the
+  // counter).  The last wave of the XCD to run out resets the counters for
+  // the next launch.  A range with a wave for every item uses no counter.
   const int xcd = blockIdx.x & 7;
-  const int it_end = a.xcd_begin[xcd + 1];
-  const int it_step = (gridDim.x >> 3) * NW;
-  for (int it = a.xcd_begin[xcd] + (blockIdx.x >> 3) * NW + wave; it < it_end; it += it_step) {
+  const int waves = (int)((gridDim.x - xcd + 7) >> 3) * NW;  // this XCD's waves
+  const int widx = (int)(blockIdx.x >> 3) * NW + wave;       // this wave among them
+  const int it_beg = a.xcd_begin[xcd], it_end = a.xcd_begin[xcd + 1];
+  const int n_it = it_end - it_beg;
+  const bool handout = a.handout && n_it > waves;
+  // items each wave takes by index: without hand-out, all of its share
+  const int spw = handout ? max(1, (int)((long)n_it * 9 / 10 / waves)) : (n_it + waves - 1) / waves;
+  const int it_dyn = it_beg + spw * waves;                                    // first handed-out item
+  // The ticket for the wave's first handed-out item is drawn when its last
+  // item by index starts (then at each handed-out item's start) and read
+  // when that item ends, so the atomic's round trip hides behind the item.
+  int ticket = 0;
+  int k = 0;
+  for (int it = it_beg + widx; it < it_end;
+       it = ++k < spw ? it_beg + widx + k * waves
+                      : (handout ? it_dyn + __builtin_amdgcn_readfirstlane(ticket) : it_end)) {
+    if (handout && k + 1 >= spw && lane == 0) ticket = atomicAdd(a.work + xcd, 1);
     const int b = vol_of_item(a, it);
     const VolDev vd = ld_const(a.vols + b);
     const int r = it - a.item_begin[b];
@@ -530,6 +552,13 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
 #pragma unroll
     for (int k = 0; k < PT; ++k)
       if (live[k]) wave_tile_store<NV>(pr[k], tile, acc[k]);
+  }
+  if (handout && lane == 0) {
+    __threadfence();
+    if (atomicAdd(a.work + 8 + xcd, 1) == waves - 1) {
+      atomicExch(a.work + xcd, 0);
+      atomicExch(a.work + 8 + xcd, 0);
+    }
   }
 }
 

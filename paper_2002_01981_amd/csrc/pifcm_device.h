@@ -84,6 +84,11 @@ struct LaunchArgs {
   int32_t xcd_begin[9];  // items [xcd_begin[k], xcd_begin[k + 1]) go to the
                          // work groups with blockIdx.x % 8 == k (one XCD):
                          // contiguous ranges of about equal work
+  int32_t* work;         // fused step: [0, 8) next item of each XCD's range,
+                         // [8, 16) its waves that have run out of items;
+                         // zero between launches (the last wave resets them)
+  int32_t handout;       // 1: the fused step may hand out items by counter
+  int32_t pad3;
   const RingOff* ring; // general-neighbourhood offsets (ring kernel only)
   int32_t nring;       // number of offsets
   int32_t pad1;

@@ -63,6 +63,7 @@ struct pifcm_ctx {
   DevBuf ring_tab;                                     // general-neighbourhood offsets
   DevBuf conf;                                         // pifcm_confusion counts
   DevBuf pso_state;                                    // pifcm_pso_interleaved states
+  DevBuf work;                                         // fused step's item counters (16 ints)
   int ring_n = 0;                                      // offsets in ring_tab
   int ring_gen = 0;                                    // rebuilds of ring_tab
   int ring_key[3] = {0, -1, 0};                        // (V, flags, bits of h) of ring_tab
@@ -143,6 +144,9 @@ pifcm_status begin(pifcm_ctx* ctx) {
   HIPCHK(hipSetDevice(ctx->device));
   HIPCHK(hipEventRecord(ctx->ev_in, ctx->user));
   HIPCHK(hipStreamWaitEvent(ctx->s, ctx->ev_in, 0));
+  // The fused step's item counters start every call at zero (each launch
+  // also leaves them at zero).
+  HIPCHK(hipMemsetAsync(ctx->work.p, 0, 16 * sizeof(int32_t), ctx->s));
   return PIFCM_OK;
 }
 
@@ -538,6 +542,11 @@ LaunchArgs make_args(const pifcm_ctx* ctx, const VolDev* vols_dev, const PairDev
   a.q2_sqdist = (p->flags & PIFCM_Q2_SQDIST) ? 1 : 0;
   a.m = p->m;
   a.use_1d = kind == kFcm ? 1 : 0;  // the pointwise kernel's 1D tiles
+  a.work = (int32_t*)ctx->work.p;
+  // Items are handed out by counter only when every pair runs every
+  // iteration: under a stop rule the items of stopped pairs cost nothing,
+  // and waves running through them would queue on the counter.
+  a.handout = p->eps == 0.f ? 1 : 0;
   if (is_ring(kind)) {
     a.ring = (const RingOff*)ctx->ring_tab.p;
     a.nring = ctx->ring_n;
@@ -694,6 +703,12 @@ pifcm_status pifcm_create(int device, void* hip_stream, pifcm_ctx** out) {
   }
   ensure(ctx, ctx->tvol, sizeof(VolDev) * kMaxBatchVols, "volume table");
   ensure(ctx, ctx->tpair, sizeof(PairDev) * kMaxPairs, "pair table");
+  if (ensure(ctx, ctx->work, 16 * sizeof(int32_t), "item counters") != PIFCM_OK ||
+      hipMemset(ctx->work.p, 0, 16 * sizeof(int32_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    pifcm_destroy(ctx);
+    return PIFCM_E_OOM;
+  }
   // The device address of the no-allocation scratch, once per device (a
   // failure here is reported by ifcm_solve_noalloc, which asks again), and
   // the pinned host staging that solve uses (it only ever grows).
@@ -716,7 +731,7 @@ void pifcm_destroy(pifcm_ctx* ctx) {
   for (DevBuf* b : {&ctx->invg, &ctx->rinv, &ctx->ubuf, &ctx->partials, &ctx->states, &ctx->jhist, &ctx->tvol,
                     &ctx->tpair, &ctx->flags, &ctx->adj_ck, &ctx->adj_seg, &ctx->adj_bar,
                     &ctx->adj_pq, &ctx->adj_misc, &ctx->adj_rs, &ctx->tune_u0, &ctx->tune_state, &ctx->tune_ref, &ctx->ring_tab,
-                    &ctx->conf, &ctx->pso_state})
+                    &ctx->conf, &ctx->pso_state, &ctx->work})
     if (b->p) (void)hipFree(b->p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);

@@ -239,6 +239,37 @@ def test_swarm_batched_equals_plain_and_oracle(ctx):
             assert rel(bat["centres"][b, q], o["c"]) <= TOL
 
 
+def test_swarm_stop_rule_many_items_per_wave(ctx):
+    """A batched swarm under the stop rule with several times more tile items
+    than the grid has waves, so every wave walks a run of items: every pair
+    against the oracle.  Where the two stop at different iterations (the
+    largest membership change within rounding of eps), the pair is checked
+    against the oracle run for the GPU's iteration count instead."""
+    shapes = [(64, 96, 128), (40, 72, 100)]
+    raws, p, po, xs, inits, parts = _swarm_case(ctx, shapes, P=48, eps=1e-3, max_iter=10, seed=70)
+    c0 = np.stack([c for c, _ in inits])
+    U0 = [u for _, u in inits]
+    xg = [x for _, x in xs]
+    bat = ctx.swarm_evaluate(xg, p, parts, c0, U0)
+    assert np.all(bat["iters"] >= 1)
+    assert len(np.unique(bat["iters"])) > 1, "every pair stopped together: the stop rule is not exercised"
+    ties = 0
+    for b, (xo, _) in enumerate(xs):
+        U0o = host(U0[b]).astype(np.float64)
+        for q in range(parts.shape[0]):
+            lam, xi = (float(v) for v in parts[q])
+            o = oracle.solve(xo, c0[b].astype(np.float64), po, lam, xi, U0=U0o)
+            n = int(bat["iters"][b, q])
+            if n != o["iters"]:
+                ties += 1
+                assert abs(n - o["iters"]) == 1, (b, q, n, o["iters"])
+                o = oracle.solve(xo, c0[b].astype(np.float64),
+                                 oracle.Params(C=4, m=2.0, eps=0.0, max_iter=n), lam, xi, U0=U0o)
+            assert abs(bat["fitness"][b, q] - o["J"]) <= TOL * abs(o["J"]), (b, q)
+            assert rel(bat["centres"][b, q], o["c"]) <= TOL, (b, q)
+    assert ties <= 3, f"{ties} pairs stopped at another iteration than the oracle's"
+
+
 def test_swarm_matches_solve(ctx):
     """A pair of the batched launch and a lone solve with the same tile
     shapes run the same arithmetic in the same order: bit-identical."""
