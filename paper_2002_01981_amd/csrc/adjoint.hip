@@ -648,8 +648,21 @@ __global__ __launch_bounds__(1024) void k_adj_finalize(const float* parts, int n
   double d[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) d[k] = 0.0;
-#pragma unroll 4
-  for (int s = threadIdx.x; s < nslots; s += 1024) {
+  // Slots s, s + 1024, ... added in that order, four loaded at once.
+  constexpr int kU = 4;
+  int s = threadIdx.x;
+  for (; s + (kU - 1) * 1024 < nslots; s += kU * 1024) {
+    float v[kU][NV];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) v[u][k] = parts[(size_t)(s + u * 1024) * NV + k];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) d[k] += (double)v[u][k];
+  }
+  for (; s < nslots; s += 1024) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) d[k] += (double)parts[(size_t)s * NV + k];
   }

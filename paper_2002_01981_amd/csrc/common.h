@@ -325,7 +325,23 @@ __global__ __launch_bounds__(256) void k_finalize(const LaunchArgs a) {
 #pragma unroll
   for (int k = 0; k < NV; ++k) d[k] = 0.0;
   const gfloat* parts = as_global(pr.partials);
-  for (int s = threadIdx.x; s < tiles; s += 256) {
+  // Each thread adds the slots s, s + 256, s + 512, ... in that order; eight
+  // of them are loaded at once so their latencies overlap (the order of the
+  // additions, and so the result, is that of the plain strided loop).
+  constexpr int kU = 8;
+  int s = threadIdx.x;
+  for (; s + (kU - 1) * 256 < tiles; s += kU * 256) {
+    float v[kU][NV];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) v[u][k] = parts[(size_t)(s + u * 256) * NV + k];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) d[k] += (double)v[u][k];
+  }
+  for (; s < tiles; s += 256) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) d[k] += (double)parts[(size_t)s * NV + k];
   }

@@ -883,6 +883,11 @@ pifcm_status solve_run(pifcm_ctx* ctx, const SolveWs& ws, const pifcm_volume* vo
   pr.U0 = U_in ? U_in : ws.ubuf;
   pr.Ua = U_out;
   pr.Ub = ws.ubuf;
+  // Odd iterations write Ua, even ones Ub: when the run is expected to end
+  // on an even iteration (no stop rule, an even count) and ws.ubuf is free
+  // at the start (U_in given), the buffers swap so the last state lands in
+  // U_out without a copy.
+  if (U_in && p->eps == 0.f && (p->max_iter & 1) == 0) std::swap(pr.Ua, pr.Ub);
   pr.st = ws.st;
   pr.partials = ws.partials;
 
@@ -1427,10 +1432,12 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
   const size_t rs_states = ((size_t)std::max(R, 1) * sizeof(SolveState) + 255) / 256 * 256;
   const size_t rs_bytes = rs_states + (size_t)std::max(R, 1) * sizeof(PairDev);
   TRY(ensure(ctx, ctx->adj_rs, rs_bytes, "recompute states"));
+  TRY(ensure(ctx, ctx->tpair, (size_t)K * sizeof(PairDev), "pair records"));
   const size_t pin_fixed = (size_t)(S + 2) * (sizeof(SolveState) + sizeof(PairDev)) + sizeof(VolDev) +
                            (size_t)(K + 1) * C * sizeof(float) + 64 * sizeof(double) + 4096;
   const size_t pin_rs = (pin_fixed + 255) / 256 * 256;  // pinned copy of the recompute records
-  const size_t pin_need = pin_rs + rs_bytes;
+  const size_t pin_fwd = (pin_rs + rs_bytes + 255) / 256 * 256;  // ... and of the forward's
+  const size_t pin_need = pin_fwd + (size_t)K * sizeof(PairDev);
   TRY(ensure_pinned(ctx, pin_need));
   char* misc = (char*)ctx->adj_misc.p;
   float* adj_parts = (float*)misc;
@@ -1451,18 +1458,30 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
   SolveState hs = init_state(centres0, C, lambda, xi, &pf, (double*)ctx->jhist.p);
   hs.B_hist = B_hist;
   hs.c_hist = c_hist;
-  PairDev pr{};
-  pr.U0 = U0;
-  pr.Ua = ubA;
-  pr.Ub = ubB;
-  pr.st = st_dev;
-  pr.partials = (float*)ctx->partials.p;
+  // Iteration t (1-based) reads state t - 1 and writes state t.  A state
+  // t = S, 2S, ... <= K - 1 is written straight into its checkpoint; the
+  // others alternate between ubA (odd t) and ubB (even t), so no iteration
+  // writes the buffer it reads.  Each iteration has its own pair record,
+  // with its input and output in the fields the kernels read for the
+  // iteration's parity (u_in_of, u_out_of).
+  auto ckpt = [&](int t) -> float* { return (float*)((char*)ctx->adj_ck.p + (size_t)(t / S - 1) * UB); };
+  auto fwd_out = [&](int t) -> float* { return (t % S == 0 && t <= K - 1) ? ckpt(t) : ((t & 1) ? ubA : ubB); };
+  PairDev* hrec = (PairDev*)(pin + pin_fwd);
+  for (int t = 1; t <= K; ++t) {
+    PairDev q{};
+    q.st = st_dev;
+    q.partials = (float*)ctx->partials.p;
+    float* in = t == 1 ? nullptr : fwd_out(t - 1);
+    q.U0 = t == 1 ? U0 : in;
+    q.Ua = (t & 1) ? fwd_out(t) : in;
+    q.Ub = (t & 1) ? (t == 1 ? fwd_out(t) : in) : fwd_out(t);
+    hrec[t - 1] = q;
+  }
   std::memcpy(pin, &hs, sizeof hs);
-  std::memcpy(pin + sizeof(SolveState), &pr, sizeof pr);
   std::memcpy(pin + sizeof(SolveState) + sizeof(PairDev), &vh[0], sizeof(VolDev));
   std::memcpy(pin + sizeof(SolveState) + sizeof(PairDev) + sizeof(VolDev), centres0, C * sizeof(float));
   HIPCHK(hipMemcpyAsync(st_dev, pin, sizeof hs, hipMemcpyHostToDevice, ctx->s));
-  HIPCHK(hipMemcpyAsync(tp, pin + sizeof(SolveState), sizeof pr, hipMemcpyHostToDevice, ctx->s));
+  HIPCHK(hipMemcpyAsync(tp, hrec, (size_t)K * sizeof(PairDev), hipMemcpyHostToDevice, ctx->s));
   HIPCHK(hipMemcpyAsync(ctx->tvol.p, pin + sizeof(SolveState) + sizeof(PairDev), sizeof(VolDev),
                         hipMemcpyHostToDevice, ctx->s));
   HIPCHK(hipMemcpyAsync(c_hist, pin + sizeof(SolveState) + sizeof(PairDev) + sizeof(VolDev),
@@ -1472,12 +1491,11 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
   const int grid = grid_for(ctx, a.nitems, occ, items_per_group(kind, ts.nw));
   const int occe = occupancy_of(kind, C, ts.nw, m2, false);
   const int gride = grid_for(ctx, a.nitems, occe, items_per_group(kind, ts.nw));
-  auto ckpt = [&](int t) -> float* { return (float*)((char*)ctx->adj_ck.p + (size_t)(t / S - 1) * UB); };
-  for (int t = 0; t < K; ++t) {
+  for (int t = 1; t <= K; ++t) {
+    a.pairs = tp + (t - 1);
     HIPCHK(launch_step(C, a, grid, ts.nw, m2, kind, true, ctx->s));
-    if ((t + 1) % S == 0 && t + 1 <= K - 1)
-      HIPCHK(hipMemcpyAsync(ckpt(t + 1), u_out_of(pr, t + 1), UB, hipMemcpyDeviceToDevice, ctx->s));
   }
+  // The objective of state K, through the last iteration's record.
   HIPCHK(launch_step(C, a, gride, ts.nw, m2, kind, false, ctx->s));
   SolveState* hst = (SolveState*)pin;
   float* hc = (float*)(pin + (size_t)(S + 2) * (sizeof(SolveState) + sizeof(PairDev)) + sizeof(VolDev));
@@ -1485,7 +1503,7 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
   HIPCHK(hipMemcpyAsync(hc, c_hist, (size_t)(K + 1) * C * sizeof(float), hipMemcpyDeviceToHost, ctx->s));
   HIPCHK(hipStreamSynchronize(ctx->s));
   const double J = hst->J_eval;
-  const float* UK = u_state_of(pr, K);
+  const float* UK = fwd_out(K);
   std::vector<float> chost(hc, hc + (size_t)(K + 1) * C);
 
   // --------------------------------------------------------------- backward
