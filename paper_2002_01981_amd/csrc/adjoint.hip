@@ -32,12 +32,12 @@
 namespace pifcm {
 
 // Tiles of both tiled adjoint kernels: a wave owns 16 x 4 columns of a tile
-// of kAdjZc planes and walks it along z; each plane plus a one-voxel halo is
-// staged once in the wave's LDS.
+// of AdjArgs::zc planes and walks it along z; each plane plus a one-voxel
+// halo is staged once in the wave's LDS.
 constexpr int kAdjTX = 16, kAdjTY = 4, kAdjHX = kAdjTX + 2, kAdjHY = kAdjTY + 2;
 constexpr int kAdjCells = kAdjHX * kAdjHY;   // 108 cells per staged plane
 constexpr int kAdjHalo = kAdjCells - 64;     // 44 halo cells, one per lane
-constexpr int kAdjZc = 64;                   // planes per tile
+constexpr int kAdjMinZc = 32;                // shallowest tile depth (fewer planes only when nz is)
 // Waves per work group: as many (up to 4) as the staged planes of each wave
 // leave room for in LDS.
 constexpr int kAdjPW = 4;                    // waves per work group of k_adj_point
@@ -110,7 +110,8 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
   const float wEb = a.q2_sqdist ? 2.f : 4.f, wCb = a.q2_sqdist ? 3.f : 9.f;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int ntx = (nx + kAdjTX - 1) / kAdjTX, nty = (ny + kAdjTY - 1) / kAdjTY;
-  const int ntz = (nz + kAdjZc - 1) / kAdjZc;
+  const int zc = a.zc;
+  const int ntz = (nz + zc - 1) / zc;
   const int nitems = ntx * nty * ntz;
   const uint32_t psz = (uint32_t)nx * (uint32_t)ny;
   const float m = a.m;
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(64 * kAdjPW) void k_adj_point(const AdjArgs a) {
     const int tyi = rest % nty;
     const int tzi = rest / nty;
     const int x0 = txi * kAdjTX, y0 = tyi * kAdjTY;
-    const int zlo = tzi * kAdjZc, zhi = min(zlo + kAdjZc, nz);
+    const int zlo = tzi * zc, zhi = min(zlo + zc, nz);
     const int gx = x0 + tx, gy = y0 + ty;
     const bool active = gx < nx && gy < ny;
     const int hx = x0 - 1 + hcx, hy = y0 - 1 + hcy;
@@ -435,7 +436,8 @@ __global__ __launch_bounds__(64 * adj_waves<C>()) void k_adj_transpose_tiled(con
   const float wEb = a.q2_sqdist ? 2.f : 4.f, wCb = a.q2_sqdist ? 3.f : 9.f;  // off-plane
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int ntx = (nx + kAdjTX - 1) / kAdjTX, nty = (ny + kAdjTY - 1) / kAdjTY;
-  const int ntz = (nz + kAdjZc - 1) / kAdjZc;
+  const int zc = a.zc;
+  const int ntz = (nz + zc - 1) / zc;
   const int nitems = ntx * nty * ntz;
   const uint32_t psz = (uint32_t)nx * (uint32_t)ny;
 
@@ -449,7 +451,7 @@ __global__ __launch_bounds__(64 * adj_waves<C>()) void k_adj_transpose_tiled(con
     const int tyi = rest % nty;
     const int tzi = rest / nty;
     const int x0 = txi * kAdjTX, y0 = tyi * kAdjTY;
-    const int zlo = tzi * kAdjZc, zhi = min(zlo + kAdjZc, nz);
+    const int zlo = tzi * zc, zhi = min(zlo + zc, nz);
     const int gx = x0 + tx, gy = y0 + ty;
     const bool active = gx < nx && gy < ny;
     const int hx = x0 - 1 + hcx, hy = y0 - 1 + hcy;
@@ -690,13 +692,40 @@ __global__ __launch_bounds__(1024) void k_adj_finalize(const float* parts, int n
   }
 }
 
+// Planes per tile of a tiled adjoint kernel whose resident work groups hold
+// `resident` waves: among the depths ceil(nz / k) of at least
+// min(nz, kAdjMinZc) planes, the one whose tiles take the fewest rounds of
+// the resident waves times (depth + 3) (a tile also stages its two halo
+// planes and fills its pipeline); the deepest of equal ones.  A shallower
+// tile spreads a volume over more waves when one tile per column leaves
+// wave slots empty.
+static int adj_depth(int nx, int ny, int nz, long resident) {
+  const long txy = (long)((nx + kAdjTX - 1) / kAdjTX) * ((ny + kAdjTY - 1) / kAdjTY);
+  const int floor_zc = std::min(nz, kAdjMinZc);
+  resident = std::max(1L, resident);
+  int best = nz;
+  long best_cost = -1;
+  for (int k = 1; k <= nz; ++k) {
+    const int d = (nz + k - 1) / k;
+    if (d < floor_zc) break;
+    if (k > 1 && d == (nz + k - 2) / (k - 1)) continue;  // same depth as k - 1
+    const long items = txy * ((nz + d - 1) / d);
+    const long cost = (items + resident - 1) / resident * (d + 3);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = d;
+    }
+  }
+  return best;
+}
+
 // Persistent grid of a tiled adjoint kernel with `waves` waves per work
 // group: one tile per wave while that fits in 8 rounds of the resident work
 // groups, else the resident work groups; a multiple of 8 (one share per
 // XCD), at least 8.
 static long adj_grid(const AdjArgs& a, int waves, int occ) {
   const long ntiles = (long)((a.nx + kAdjTX - 1) / kAdjTX) * ((a.ny + kAdjTY - 1) / kAdjTY) *
-                      ((a.nz + kAdjZc - 1) / kAdjZc);
+                      ((a.nz + a.zc - 1) / a.zc);
   const long want = (ntiles + waves - 1) / waves;
   const long resident = (long)std::max(occ, 1) * std::max(1, a.num_cu);
   const long g = want <= 8 * resident ? (want + 7) / 8 * 8 : resident / 8 * 8;
@@ -721,13 +750,15 @@ static hipError_t launch_adj_c(const AdjArgs& a, bool m2, bool eval, float* Ubar
                                : reinterpret_cast<const void*>(&k_adj_point<C, false, false>));
     int& o = occ[(eval ? 2 : 0) + (m2 ? 1 : 0)];
     if (!o) o = occupancy_of(f, 64 * kAdjPW);
-    const int g = (int)adj_grid(a, kAdjPW, o);
+    AdjArgs ap = a;
+    ap.zc = adj_depth(a.nx, a.ny, a.nz, (long)o * std::max(1, a.num_cu) * kAdjPW);
+    const int g = (int)adj_grid(ap, kAdjPW, o);
     if (eval) {
-      if (m2) hipLaunchKernelGGL((k_adj_point<C, true, true>), dim3(g), dim3(64 * kAdjPW), 0, s, a);
-      else hipLaunchKernelGGL((k_adj_point<C, false, true>), dim3(g), dim3(64 * kAdjPW), 0, s, a);
+      if (m2) hipLaunchKernelGGL((k_adj_point<C, true, true>), dim3(g), dim3(64 * kAdjPW), 0, s, ap);
+      else hipLaunchKernelGGL((k_adj_point<C, false, true>), dim3(g), dim3(64 * kAdjPW), 0, s, ap);
     } else {
-      if (m2) hipLaunchKernelGGL((k_adj_point<C, true, false>), dim3(g), dim3(64 * kAdjPW), 0, s, a);
-      else hipLaunchKernelGGL((k_adj_point<C, false, false>), dim3(g), dim3(64 * kAdjPW), 0, s, a);
+      if (m2) hipLaunchKernelGGL((k_adj_point<C, true, false>), dim3(g), dim3(64 * kAdjPW), 0, s, ap);
+      else hipLaunchKernelGGL((k_adj_point<C, false, false>), dim3(g), dim3(64 * kAdjPW), 0, s, ap);
     }
     hipLaunchKernelGGL((k_adj_finalize<C>), dim3(1), dim3(1024), 0, s, a.partials, g * kAdjPW, cbar_out,
                        acc2);
@@ -740,12 +771,14 @@ static hipError_t launch_adj_c(const AdjArgs& a, bool m2, bool eval, float* Ubar
       o = occupancy_of(eval ? reinterpret_cast<const void*>(&k_adj_transpose_tiled<C, true>)
                             : reinterpret_cast<const void*>(&k_adj_transpose_tiled<C, false>),
                        64 * adj_waves<C>());
-    const long g = adj_grid(a, adj_waves<C>(), o);
+    AdjArgs at = a;
+    at.zc = adj_depth(a.nx, a.ny, a.nz, (long)o * std::max(1, a.num_cu) * adj_waves<C>());
+    const long g = adj_grid(at, adj_waves<C>(), o);
     if (eval)
-      hipLaunchKernelGGL((k_adj_transpose_tiled<C, true>), dim3((int)g), dim3(64 * adj_waves<C>()), 0, s, a,
+      hipLaunchKernelGGL((k_adj_transpose_tiled<C, true>), dim3((int)g), dim3(64 * adj_waves<C>()), 0, s, at,
                          Ubar_out);
     else
-      hipLaunchKernelGGL((k_adj_transpose_tiled<C, false>), dim3((int)g), dim3(64 * adj_waves<C>()), 0, s, a,
+      hipLaunchKernelGGL((k_adj_transpose_tiled<C, false>), dim3((int)g), dim3(64 * adj_waves<C>()), 0, s, at,
                          Ubar_out);
   }
   return hipGetLastError();
@@ -766,10 +799,11 @@ hipError_t launch_adjoint(int C, const AdjArgs& a, bool m2, bool eval, float* Ub
 }
 
 // Upper bound of the slots k_adj_point writes (its grid never exceeds the
-// one-tile-per-wave grid, at least 8 work groups).
+// one-tile-per-wave grid of the shallowest depth, at least 8 work groups).
 size_t adjoint_slots(int nx, int ny, int nz) {
+  const int zmin = std::max(1, std::min(nz, kAdjMinZc));
   const long ntiles = (long)((nx + kAdjTX - 1) / kAdjTX) * ((ny + kAdjTY - 1) / kAdjTY) *
-                      ((nz + kAdjZc - 1) / kAdjZc);
+                      ((nz + zmin - 1) / zmin);
   const long want = (ntiles + kAdjPW - 1) / kAdjPW;
   return (size_t)std::max<long>(8, (want + 7) / 8 * 8) * kAdjPW;
 }

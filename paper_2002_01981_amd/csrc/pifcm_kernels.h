@@ -72,6 +72,7 @@ struct AdjArgs {
   float* Ubar_direct;      // [N][C] direct term of the objective-only pass
   float* partials;         // [adjoint_slots][C + 2] per-wave sums
   int32_t num_cu;          // compute units of the device (grid sizing)
+  int32_t zc;              // planes per tile (set per kernel by launch_adjoint)
 };
 // Reverse of one iteration (eval = false) or of the final objective (eval =
 // true): writes dJ/dc of that state to cbar_out[C], adds dJ/dlambda and

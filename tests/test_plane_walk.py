@@ -255,8 +255,12 @@ def test_two_ring_walk(nzs):
 
 @pytest.mark.parametrize("nzs", NZ_CHUNKS, ids=lambda r: f"nz{r.start}-{r.stop - 1}")
 def test_adjoint_walk(nzs):
+    """The adjoint kernels' depth is some ceil(nz / k) of at least
+    min(nz, 32) planes, picked per launch from the kernel's occupancy."""
     for nz in nzs:
-        check(adjoint_walk, nz, 0, nz, 64)
+        depths = {(nz + k - 1) // k for k in range(1, nz + 1)}
+        for zc in sorted(d for d in depths if d >= min(nz, 32)) + [64]:
+            check(adjoint_walk, nz, 0, nz, zc)
 
 
 def test_discarded_prefetch_variant_is_caught():
