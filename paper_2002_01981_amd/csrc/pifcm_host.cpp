@@ -1465,7 +1465,15 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
   // with its input and output in the fields the kernels read for the
   // iteration's parity (u_in_of, u_out_of).
   auto ckpt = [&](int t) -> float* { return (float*)((char*)ctx->adj_ck.p + (size_t)(t / S - 1) * UB); };
-  auto fwd_out = [&](int t) -> float* { return (t % S == 0 && t <= K - 1) ? ckpt(t) : ((t & 1) ? ubA : ubB); };
+  // States of the last segment (t0_last < t < K) go straight into the
+  // segment buffers the reverse sweep would recompute them into.
+  auto seg_state = [&](int i) -> float* { return (float*)((char*)ctx->adj_seg.p + (size_t)(i - 1) * UB); };
+  const int t0_last = ((K - 1) / S) * S;
+  auto fwd_out = [&](int t) -> float* {
+    if (t % S == 0 && t <= K - 1) return ckpt(t);
+    if (t > t0_last && t < K) return seg_state(t - t0_last);
+    return (t & 1) ? ubA : ubB;
+  };
   PairDev* hrec = (PairDev*)(pin + pin_fwd);
   for (int t = 1; t <= K; ++t) {
     PairDev q{};
@@ -1531,10 +1539,10 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
   float* cur = bar0;
   float* other = bar1;
   // Recomputed states of the current segment: seg[i] = U^(t0 + i), computed
-  // by one forward iteration U^(t0+i-1) -> U^(t0+i) with c^(t0+i-1) each.
-  // Their state and pair records are written once, here, and uploaded in one
-  // copy, so the reverse sweep below only enqueues work.
-  auto seg_state = [&](int i) -> float* { return (float*)((char*)ctx->adj_seg.p + (size_t)(i - 1) * UB); };
+  // by one forward iteration U^(t0+i-1) -> U^(t0+i) with c^(t0+i-1) each
+  // (the last segment's are still there from the forward pass).  Their state
+  // and pair records are written once, here, and uploaded in one copy, so
+  // the reverse sweep below only enqueues work.
   SolveState* rs_st = (SolveState*)ctx->adj_rs.p;
   PairDev* rs_pr = (PairDev*)((char*)ctx->adj_rs.p + rs_states);
   {
@@ -1570,8 +1578,11 @@ pifcm_status ifcm_backward(pifcm_ctx* ctx, const pifcm_volume* vol, const pifcm_
       seg[0] = t0 == 0 ? U0 : ckpt(t0);
       const int len = std::min(S, K - t0);
       for (int i = 1; i < len; ++i) {
-        const LaunchArgs ar = make_args(ctx, (const VolDev*)ctx->tvol.p, rs_pr + seg_r + (i - 1), vh, 1, 1, kind, p);
-        HIPCHK(launch_step(C, ar, grid, ts.nw, m2, kind, true, ctx->s));
+        if (t0 != t0_last) {
+          const LaunchArgs ar =
+              make_args(ctx, (const VolDev*)ctx->tvol.p, rs_pr + seg_r + (i - 1), vh, 1, 1, kind, p);
+          HIPCHK(launch_step(C, ar, grid, ts.nw, m2, kind, true, ctx->s));
+        }
         seg[i] = seg_state(i);
       }
       seg_t0 = t0;
