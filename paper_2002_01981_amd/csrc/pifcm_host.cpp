@@ -778,7 +778,8 @@ pifcm_status pifcm_workspace_bytes(pifcm_ctx* ctx, int64_t* device_bytes, int64_
   for (const DevBuf* b : {&ctx->invg, &ctx->rinv, &ctx->ubuf, &ctx->partials, &ctx->states, &ctx->jhist,
                           &ctx->tvol, &ctx->tpair, &ctx->flags, &ctx->adj_ck, &ctx->adj_seg,
                           &ctx->adj_bar, &ctx->adj_pq, &ctx->adj_misc, &ctx->adj_rs, &ctx->tune_u0,
-                          &ctx->tune_state, &ctx->tune_ref, &ctx->ring_tab, &ctx->conf, &ctx->pso_state})
+                          &ctx->tune_state, &ctx->tune_ref, &ctx->ring_tab, &ctx->conf, &ctx->pso_state,
+                          &ctx->work})
     d += (int64_t)b->cap;
   if (device_bytes) *device_bytes = d;
   if (pinned_bytes) *pinned_bytes = (int64_t)ctx->pinned_cap;
