@@ -3,14 +3,15 @@
 5 iterations.
 
 - The adjoint's gradient of J_K with respect to (lambda, xi, c^0) against
-  central differences of the FP64 oracle's J_K (h = 1e-4) at (0.2, 0.3).
+  central differences of the FP64 oracle's J_K (h = 1e-4) at (0.2, 0.3),
+  (0.4, 0.1) and (0.1, 0.6).
 - Algorithm 1 steps 4-9 followed by the gradient hand-off: a 32-particle,
   10-generation swarm whose fitness is J_K, then projected gradient steps
   from its global best (refine), checked against the oracle's J_K at the
   point reached.
 
 Each oracle J_K at this size costs a few seconds of host time (about a
-minute for the 13 of the central differences)."""
+minute for the 13 of the central differences at each point)."""
 import numpy as np
 import pytest
 
@@ -48,10 +49,11 @@ def brain(ctx):
 
 
 @pytest.mark.timeout(600)
-def test_adjoint_full_size_against_oracle_differences(ctx, brain):
+@pytest.mark.parametrize("point", [0, 1, 2])
+def test_adjoint_full_size_against_oracle_differences(ctx, brain, point):
     W, xo, xg, c0, U0 = brain
     K, s = W["K"], W["ckpt"]
-    lam, xi = W["points"][0]
+    lam, xi = W["points"][point]
     print(f"adjoint vs oracle differences: {xo.shape}, K = {K}, ({lam}, {xi})", flush=True)
     g = ctx.ifcm_backward(xg, _P(C=4, m=2.0), lam, xi, c0, U0, K, s)
     po = oracle.Params(C=4, m=2.0, eps=0.0, max_iter=K)
