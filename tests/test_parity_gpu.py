@@ -270,6 +270,52 @@ def test_swarm_stop_rule_many_items_per_wave(ctx):
     assert ties <= 3, f"{ties} pairs stopped at another iteration than the oracle's"
 
 
+@pytest.mark.parametrize("C,m", [(2, 1.7), (3, 2.0), (4, 2.5), (6, 2.0)])
+def test_swarm_other_cluster_counts_and_fuzziness(ctx, C, m):
+    """Batched and plain swarm evaluation at cluster counts and fuzzifiers
+    other than the benchmark's (one particle per work item, the general-m
+    memberships of eq (2)), under the stop rule: the two modes bit-identical,
+    every pair against the oracle (a pair that stops one iteration apart
+    from the oracle, its largest change within rounding of eps, is checked
+    at the GPU's iteration count)."""
+    from paper_2002_01981_amd import PIFCM_SWARM_BATCHED, PIFCM_SWARM_PLAIN
+    shapes = [(9, 21, 66), (14, 10, 37)]
+    eps, T = 1e-5, 12
+    p = _P(C=C, m=m, eps=eps, max_iter=T)
+    po = oracle.Params(C=C, m=m, eps=eps, max_iter=T)
+    xs, c0, U0 = [], [], []
+    for b, shape in enumerate(shapes):
+        raw = synth.random_ellipsoids(shape=shape, seed=80 + b, sigma=0.07)[0]
+        xo, xg = _both_normalised(ctx, raw)
+        cg, Ug, _ = ctx.pifcm_fcm_init(xg, _P(C=C, m=m, eps=0.0, max_iter=10))
+        xs.append((xo, xg))
+        c0.append(cg)
+        U0.append(Ug)
+    c0 = np.stack(c0)
+    parts = synth.uniform_particles(81, 5)
+    xg = [x for _, x in xs]
+    bat = ctx.swarm_evaluate(xg, p, parts, c0, U0, mode=PIFCM_SWARM_BATCHED)
+    pla = ctx.swarm_evaluate(xg, p, parts, c0, U0, mode=PIFCM_SWARM_PLAIN)
+    assert np.array_equal(bat["fitness"], pla["fitness"])
+    assert np.array_equal(bat["centres"], pla["centres"])
+    assert np.array_equal(bat["iters"], pla["iters"])
+    ties = 0
+    for b, (xo, _) in enumerate(xs):
+        U0o = host(U0[b]).astype(np.float64)
+        for q in range(parts.shape[0]):
+            lam, xi = (float(v) for v in parts[q])
+            o = oracle.solve(xo, c0[b].astype(np.float64), po, lam, xi, U0=U0o)
+            n = int(bat["iters"][b, q])
+            if n != o["iters"]:
+                ties += 1
+                assert abs(n - o["iters"]) == 1, (b, q, n, o["iters"])
+                o = oracle.solve(xo, c0[b].astype(np.float64), oracle.Params(C=C, m=m, eps=0.0, max_iter=n),
+                                 lam, xi, U0=U0o)
+            assert abs(bat["fitness"][b, q] - o["J"]) <= TOL * abs(o["J"]), (b, q)
+            assert rel(bat["centres"][b, q], o["c"]) <= TOL, (b, q)
+    assert ties <= 1
+
+
 def test_swarm_matches_solve(ctx):
     """A pair of the batched launch and a lone solve with the same tile
     shapes run the same arithmetic in the same order: bit-identical."""
