@@ -316,6 +316,47 @@ def test_swarm_other_cluster_counts_and_fuzziness(ctx, C, m):
     assert ties <= 1
 
 
+def test_swarm_counter_handout_matches_plain(ctx):
+    """Without a stop rule a batched launch whose XCD ranges hold more items
+    than the XCD has waves hands the last tenth of each range out by counter
+    (here ≈ 46 000 items of 32-plane tiles, one particle per item, against
+    ≈ 3000 resident waves): bit-identical to the plain
+    mode, which runs each pair alone with no counter, on every pair; a second
+    call (the counters reset by the first) bit-identical again; sampled pairs
+    against the oracle."""
+    from paper_2002_01981_amd import PIFCM_SWARM_BATCHED, PIFCM_SWARM_PLAIN
+    shapes = [(128, 96, 64), (100, 80, 70), (90, 60, 50)]
+    T = 5
+    p = _P(C=4, m=2.0, eps=0.0, max_iter=T)
+    xs, c0, U0 = [], [], []
+    for b, shape in enumerate(shapes):
+        raw = synth.random_ellipsoids(shape=shape, seed=90 + b, sigma=0.07)[0]
+        xo, xg = _both_normalised(ctx, raw)
+        cg, Ug, _ = ctx.pifcm_fcm_init(xg, _P(C=4, m=2.0, eps=0.0, max_iter=10))
+        xs.append((xo, xg))
+        c0.append(cg)
+        U0.append(Ug)
+    c0 = np.stack(c0)
+    P = 48
+    parts = synth.uniform_particles(91, P)
+    xg = [x for _, x in xs]
+    bat = ctx.swarm_evaluate(xg, p, parts, c0, U0, mode=PIFCM_SWARM_BATCHED)
+    again = ctx.swarm_evaluate(xg, p, parts, c0, U0, mode=PIFCM_SWARM_BATCHED)
+    pla = ctx.swarm_evaluate(xg, p, parts, c0, U0, mode=PIFCM_SWARM_PLAIN)
+    for other in (again, pla):
+        assert np.array_equal(bat["fitness"], other["fitness"])
+        assert np.array_equal(bat["centres"], other["centres"])
+        assert np.array_equal(bat["iters"], other["iters"])
+    assert np.all(bat["iters"] == T)
+    po = oracle.Params(C=4, m=2.0, eps=0.0, max_iter=T)
+    for b, q in ((0, 0), (1, 23), (2, 47)):
+        xo = xs[b][0]
+        lam, xi = (float(v) for v in parts[q])
+        o = oracle.solve(xo, c0[b].astype(np.float64), po, lam, xi, U0=host(U0[b]).astype(np.float64))
+        assert abs(bat["fitness"][b, q] - o["J"]) <= TOL * abs(o["J"]), (b, q)
+        assert rel(bat["centres"][b, q], o["c"]) <= TOL, (b, q)
+
+
 def test_swarm_matches_solve(ctx):
     """A pair of the batched launch and a lone solve with the same tile
     shapes run the same arithmetic in the same order: bit-identical."""
