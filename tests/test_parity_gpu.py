@@ -357,6 +357,69 @@ def test_swarm_counter_handout_matches_plain(ctx):
         assert rel(bat["centres"][b, q], o["c"]) <= TOL, (b, q)
 
 
+def _tiny_batch(ctx, shapes, seed, C=4, m=2.0):
+    xs, c0, U0 = [], [], []
+    for b, shape in enumerate(shapes):
+        raw = synth.random_ellipsoids(shape=shape, seed=seed + b, sigma=0.07)[0]
+        xo, xg = _both_normalised(ctx, raw)
+        cg, Ug, _ = ctx.pifcm_fcm_init(xg, _P(C=C, m=m, eps=0.0, max_iter=10))
+        xs.append((xo, xg))
+        c0.append(cg)
+        U0.append(Ug)
+    return xs, np.stack(c0), U0
+
+
+def test_swarm_largest_batch_of_volumes(ctx):
+    """32 ragged volumes in one call (the most a launch holds), a few of them
+    a single plane or a single row, 3 particles: batched and plain
+    bit-identical, every pair against the oracle."""
+    from paper_2002_01981_amd import PIFCM_SWARM_BATCHED, PIFCM_SWARM_PLAIN
+    rng = np.random.default_rng(95)
+    shapes = [tuple(int(v) for v in rng.integers(2, 19, 3)) for _ in range(29)] + [(1, 7, 23), (6, 1, 19), (5, 9, 1)]
+    xs, c0, U0 = _tiny_batch(ctx, shapes, 300)
+    T = 4
+    p = _P(C=4, m=2.0, eps=0.0, max_iter=T)
+    parts = synth.uniform_particles(96, 3)
+    xg = [x for _, x in xs]
+    bat = ctx.swarm_evaluate(xg, p, parts, c0, U0, mode=PIFCM_SWARM_BATCHED)
+    pla = ctx.swarm_evaluate(xg, p, parts, c0, U0, mode=PIFCM_SWARM_PLAIN)
+    assert bat["fitness"].shape == (32, 3)
+    assert np.array_equal(bat["fitness"], pla["fitness"])
+    assert np.array_equal(bat["centres"], pla["centres"])
+    po = oracle.Params(C=4, m=2.0, eps=0.0, max_iter=T)
+    for b, (xo, _) in enumerate(xs):
+        for q in range(3):
+            lam, xi = (float(v) for v in parts[q])
+            o = oracle.solve(xo, c0[b].astype(np.float64), po, lam, xi, U0=host(U0[b]).astype(np.float64))
+            assert abs(bat["fitness"][b, q] - o["J"]) <= TOL * max(abs(o["J"]), 1e-30), (b, q)
+            assert rel(bat["centres"][b, q], o["c"]) <= TOL, (b, q)
+
+
+def test_swarm_largest_pair_count(ctx):
+    """B x P = 65536 (volumes x particles, the most a call takes) on small
+    volumes, one batched launch per iteration: sampled pairs equal a lone
+    solve bit for bit and the oracle."""
+    shapes = [(3, 5, 7), (2, 6, 9), (4, 4, 4), (5, 3, 8)] * 4
+    xs, c0, U0 = _tiny_batch(ctx, shapes, 400)
+    P = 65536 // len(shapes)
+    T = 3
+    p = _P(C=4, m=2.0, eps=0.0, max_iter=T)
+    parts = synth.uniform_particles(97, P)
+    xg = [x for _, x in xs]
+    bat = ctx.swarm_evaluate(xg, p, parts, c0, U0)
+    assert bat["fitness"].shape == (len(shapes), P)
+    assert np.all(np.isfinite(bat["fitness"]))
+    po = oracle.Params(C=4, m=2.0, eps=0.0, max_iter=T)
+    for b, q in ((0, 0), (5, P // 2), (15, P - 1), (9, 1234)):
+        lam, xi = (float(v) for v in parts[q])
+        s1 = ctx.ifcm_solve(xg[b], p, lam, xi, c0[b], U_in=U0[b])
+        assert s1["J"] == bat["fitness"][b, q]
+        assert np.array_equal(s1["c"], bat["centres"][b, q])
+        o = oracle.solve(xs[b][0], c0[b].astype(np.float64), po, lam, xi, U0=host(U0[b]).astype(np.float64))
+        assert abs(bat["fitness"][b, q] - o["J"]) <= TOL * abs(o["J"]), (b, q)
+        assert rel(bat["centres"][b, q], o["c"]) <= TOL, (b, q)
+
+
 def test_swarm_matches_solve(ctx):
     """A pair of the batched launch and a lone solve with the same tile
     shapes run the same arithmetic in the same order: bit-identical."""
