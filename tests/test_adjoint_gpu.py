@@ -62,17 +62,34 @@ def test_gradient_matches_finite_differences(ctx, lam, xi, K):
     assert err <= GRAD_TOL, (gg, go, err)
 
 
-def test_checkpoint_stride_does_not_change_the_gradient(ctx):
-    C, K = 4, 9
+@pytest.mark.parametrize("K,strides", [(9, (1, 2, 4, 9)), (11, (1, 3, 4, 5, 11))])
+def test_checkpoint_stride_does_not_change_the_gradient(ctx, K, strides):
+    """Any checkpoint stride gives the same gradient bit for bit, including
+    strides whose last segment is partial and holds several states (K = 11
+    with strides 3, 4, 5: the forward pass leaves those states for the
+    reverse sweep instead of their recomputation)."""
+    C = 4
     x, c0, U0 = _case((8, 12, 20), C, seed=51)
     ref = None
-    for s in (1, 2, 4, 9):
+    for s in strides:
         J, g = _gpu_grad(ctx, x, c0, U0, C, 2.0, 0.3, 0.2, K, s)
         if ref is None:
             ref = (J, g)
         else:
-            assert J == ref[0]
-            assert np.array_equal(g, ref[1])
+            assert J == ref[0], s
+            assert np.array_equal(g, ref[1]), s
+
+
+def test_gradient_partial_last_segment_against_oracle(ctx):
+    """K = 11 with checkpoints every 4: segments of 4, 4 and 3 iterations,
+    against central differences of the oracle."""
+    C, K = 4, 11
+    x, c0, U0 = _case((10, 14, 22), C, seed=53)
+    Jg, gg = _gpu_grad(ctx, x, c0, U0, C, 2.0, 0.25, 0.35, K, 4)
+    Jo, go = _fd(x, c0, U0, C, 2.0, 0.25, 0.35, K)
+    assert abs(Jg - Jo) <= 1e-4 * abs(Jo)
+    err = np.max(np.abs(gg - go)) / np.max(np.abs(go))
+    assert err <= GRAD_TOL, (gg, go, err)
 
 
 @pytest.mark.parametrize("C,m", [(3, 2.0), (4, 2.5)])
