@@ -1660,9 +1660,12 @@ pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
     double ms = 0.0;
     if (tune_cache_get(cache, key, t, ms)) {
       apply(t);
+      char tz[16];
+      if (t.zc > 0) snprintf(tz, sizeof tz, "%d", t.zc);
+      else snprintf(tz, sizeof tz, "auto");
       char desc[512];
-      snprintf(desc, sizeof desc, "waves_per_group=%d planes_per_tile=%d particles_per_item=%d step_ms=%.4f cached [%s]",
-               t.nw, shape_for(ctx, C, m2, vols[0]).zc, t.pt, ms, key.c_str());
+      snprintf(desc, sizeof desc, "waves_per_group=%d planes_per_tile=%s particles_per_item=%d step_ms=%.4f cached [%s]",
+               t.nw, tz, t.pt, ms, key.c_str());
       describe(desc);
       return PIFCM_OK;
     }
@@ -1821,10 +1824,15 @@ pifcm_status pifcm_tune(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
   ctx->tuned = saved;
   apply(best);
   if (cache && *cache) tune_cache_put(cache, key, best, best_ms);
+  // The depth reported is the one chosen (each volume clamps it to its
+  // plane count); "auto" is each volume's default depth.
+  char bz[16];
+  if (best.zc > 0) snprintf(bz, sizeof bz, "%d", best.zc);
+  else snprintf(bz, sizeof bz, "auto");
   char desc[1024];
   snprintf(desc, sizeof desc,
-           "waves_per_group=%d planes_per_tile=%d particles_per_item=%d step_ms=%.4f candidates=%zu [%s]", best.nw,
-           shape_for(ctx, C, m2, vols[0]).zc, best.pt, best_ms, cands.size(), tried.c_str());
+           "waves_per_group=%d planes_per_tile=%s particles_per_item=%d step_ms=%.4f candidates=%zu [%s]", best.nw,
+           bz, best.pt, best_ms, cands.size(), tried.c_str());
   describe(desc);
   ctx->err.clear();
   return PIFCM_OK;

@@ -144,6 +144,41 @@ def test_tune_keeps_results_and_reports_choice(ctx):
     assert rel(after["centres"][0, 2], o["c"]) <= TOL
 
 
+def test_tune_cache_file(ctx, tmp_path, monkeypatch):
+    """With PIFCM_TUNE_CACHE naming a file, the first tuning stores its
+    choice under the key of (device, C, m == 2, V, B, P, shape bucket); a new
+    context reads it back without timing, reports it as cached, and runs the
+    same decomposition: the same bits as the context that tuned."""
+    import json
+    from paper_2002_01981_amd import Context
+    xs, c0, U0 = _multi(ctx, [(12, 40, 52), (20, 17, 33)], 76)
+    p = _P(C=4, m=2.0, eps=0.0, max_iter=6)
+    parts = synth.uniform_particles(91, 8)
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("PIFCM_TUNE_CACHE", str(cache))
+    desc = ctx.pifcm_tune(xs, p, 8)
+    assert "candidates=" in desc and "cached" not in desc
+    entries = [l for l in cache.read_text().splitlines() if '"' in l and "{" in l]
+    assert len(entries) == 1
+    key = entries[0].split('"')[1]
+    assert key.split("|")[1:] == ["C4", "m2", "V1", "B2", "P8", "N2^16", "Z2^5"]
+    chosen = json.loads("{" + entries[0].strip().rstrip(",") + "}")[key]
+    assert set(chosen) == {"nw", "zc", "pt", "step_ms"}
+    tuned = ctx.swarm_evaluate(xs, p, parts, c0, U0)
+    other = Context(0)
+    try:
+        desc2 = other.pifcm_tune(xs, p, 8)
+        assert "cached" in desc2 and key in desc2
+        assert desc2.startswith(f"waves_per_group={chosen['nw']} ")
+        assert f"particles_per_item={chosen['pt']} " in desc2
+        again = other.swarm_evaluate(xs, p, parts, c0, U0)
+    finally:
+        other.close()
+    assert np.array_equal(tuned["fitness"], again["fitness"])
+    assert np.array_equal(tuned["centres"], again["centres"])
+    assert len([l for l in cache.read_text().splitlines() if '"' in l and "{" in l]) == 1
+
+
 def test_pso_interleaved_matches_oracle(ctx):
     """Particles carrying their own state, 2 iterations per generation."""
     from gpu_util import rel2, saturated
