@@ -30,6 +30,11 @@
  *     inputs are never modified, and pifcm_last_error describes the cause.
  *   - Results are deterministic: the same inputs give bit-identical outputs
  *     (all sums are taken in a fixed order; no floating-point atomics).
+ *   - A context is used by one host thread at a time.  Separate contexts
+ *     (each with its own stream and workspace) may be used from different
+ *     threads at once, on one device or several; ifcm_solve_noalloc calls
+ *     on one device share that device's scratch array and are serialised
+ *     by the library.
  */
 #ifndef PIFCM_H
 #define PIFCM_H

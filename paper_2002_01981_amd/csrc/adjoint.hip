@@ -26,6 +26,8 @@
 // k_adj_point does the per-voxel part (recomputing the forward values from
 // (U^t, c^t)), k_adj_transpose_tiled the gather of dU; the sums of dc,
 // dlambda and dxi go to per-wave slots that k_adj_finalize adds in fp64.
+#include <atomic>
+
 #include "common.h"
 #include "pifcm_kernels.h"
 
@@ -743,13 +745,19 @@ static hipError_t launch_adj_c(const AdjArgs& a, bool m2, bool eval, float* Ubar
                                double* cbar_out, double* acc2, hipStream_t s) {
   // Per-voxel part: each wave leaves its sums in slot (block, wave).
   {
-    static int occ[4] = {0, 0, 0, 0};
+    // Occupancy of each variant, found once (any thread may store it: the
+    // value is the same).
+    static std::atomic<int> occ[4] = {0, 0, 0, 0};
     const void* f = eval ? (m2 ? reinterpret_cast<const void*>(&k_adj_point<C, true, true>)
                                : reinterpret_cast<const void*>(&k_adj_point<C, false, true>))
                          : (m2 ? reinterpret_cast<const void*>(&k_adj_point<C, true, false>)
                                : reinterpret_cast<const void*>(&k_adj_point<C, false, false>));
-    int& o = occ[(eval ? 2 : 0) + (m2 ? 1 : 0)];
-    if (!o) o = occupancy_of(f, 64 * kAdjPW);
+    std::atomic<int>& oc = occ[(eval ? 2 : 0) + (m2 ? 1 : 0)];
+    int o = oc.load(std::memory_order_relaxed);
+    if (!o) {
+      o = occupancy_of(f, 64 * kAdjPW);
+      oc.store(o, std::memory_order_relaxed);
+    }
     AdjArgs ap = a;
     ap.zc = adj_depth(a.nx, a.ny, a.nz, (long)o * std::max(1, a.num_cu) * kAdjPW);
     const int g = (int)adj_grid(ap, kAdjPW, o);
@@ -765,12 +773,15 @@ static hipError_t launch_adj_c(const AdjArgs& a, bool m2, bool eval, float* Ubar
   }
   if (Ubar_out) {
     // Tiled transpose: one wave per tile, a persistent grid.
-    static int occ[2] = {0, 0};
-    int& o = occ[eval ? 1 : 0];
-    if (!o)
+    static std::atomic<int> occ[2] = {0, 0};
+    std::atomic<int>& oc = occ[eval ? 1 : 0];
+    int o = oc.load(std::memory_order_relaxed);
+    if (!o) {
       o = occupancy_of(eval ? reinterpret_cast<const void*>(&k_adj_transpose_tiled<C, true>)
                             : reinterpret_cast<const void*>(&k_adj_transpose_tiled<C, false>),
                        64 * adj_waves<C>());
+      oc.store(o, std::memory_order_relaxed);
+    }
     AdjArgs at = a;
     at.zc = adj_depth(a.nx, a.ny, a.nz, (long)o * std::max(1, a.num_cu) * adj_waves<C>());
     const long g = adj_grid(at, adj_waves<C>(), o);
