@@ -420,6 +420,29 @@ def test_swarm_largest_pair_count(ctx):
         assert rel(bat["centres"][b, q], o["c"]) <= TOL, (b, q)
 
 
+def test_swarm_graph_cache_across_alternating_calls(ctx):
+    """The batched mode replays a captured graph kept per context and keyed
+    by the launch: swarms of different shapes, particle counts and stop
+    rules called in turn (A, B, C, A, B, C) each repeat their first results
+    bit for bit."""
+    from paper_2002_01981_amd import PIFCM_SWARM_BATCHED
+    cases = []
+    for k, (shapes, P, eps, T) in enumerate((([(10, 20, 70), (7, 33, 40)], 5, 0.0, 6),
+                                             ([(16, 24, 30)], 9, 1e-5, 20),
+                                             ([(6, 9, 12), (11, 5, 8), (9, 9, 9)], 4, 0.0, 3))):
+        xs, c0, U0 = _tiny_batch(ctx, shapes, 500 + 10 * k)
+        cases.append(([x for _, x in xs], c0, U0, synth.uniform_particles(98 + k, P),
+                      _P(C=4, m=2.0, eps=eps, max_iter=T)))
+    first = [ctx.swarm_evaluate(xg, p, parts, c0, U0, mode=PIFCM_SWARM_BATCHED)
+             for xg, c0, U0, parts, p in cases]
+    for _ in range(2):
+        for (xg, c0, U0, parts, p), ref in zip(cases, first):
+            r = ctx.swarm_evaluate(xg, p, parts, c0, U0, mode=PIFCM_SWARM_BATCHED)
+            assert np.array_equal(r["fitness"], ref["fitness"])
+            assert np.array_equal(r["centres"], ref["centres"])
+            assert np.array_equal(r["iters"], ref["iters"])
+
+
 def test_swarm_matches_solve(ctx):
     """A pair of the batched launch and a lone solve with the same tile
     shapes run the same arithmetic in the same order: bit-identical."""
