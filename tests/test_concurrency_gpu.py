@@ -18,7 +18,7 @@ def _P(**kw):
     return Params(**kw)
 
 
-def _work(ctx, seed):
+def _calls(ctx, seed):
     """A batched swarm, a backward pass and a no-allocation solve on one
     context; returns their host results."""
     shapes = [(40, 48, 36), (24, 30, 52)]
@@ -47,7 +47,7 @@ def _run(seed, out, key):
     from paper_2002_01981_amd import Context
     ctx = Context(0)
     try:
-        out[key] = _work(ctx, seed)
+        out[key] = _calls(ctx, seed)
     except Exception as e:  # reported by the main thread
         out[key] = e
     finally:
