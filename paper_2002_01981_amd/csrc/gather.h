@@ -98,15 +98,16 @@ __global__ __launch_bounds__(64 * NW) void k_ifcm_gather(const LaunchArgs a) {
 
   // Items: 8 contiguous ranges of about equal work, one per XCD (work groups
   // go to the XCDs round-robin), walked in order by that XCD's waves, so
-  // neighbouring tiles run together and share L2.  When the range holds more
-  // items than the XCD has waves, each wave first takes its share of the
-  // first nine tenths by index (items w, w + W, w + 2W, ...), and the last
-  // tenth is handed out one item at a time to whichever wave is free (a
-  // counter per XCD): the tail of the launch stays balanced while the
-  // counter sees few requests (items whose particles have all stopped cost
-  // nothing, so handing every item out would make waves queue on the
-  // counter).  The last wave of the XCD to run out resets the counters for
-  // the next launch.  A range with a wave for every item uses no counter.
+  // neighbouring tiles run together and share L2: wave w of the W takes
+  // items w, w + W, w + 2W, ...  Without a stop rule (a.handout), a range
+  // holding more items than the XCD has waves is walked that way for its
+  // first nine tenths only; the last tenth is handed out one item at a time
+  // to whichever wave is free (a counter per XCD), which keeps the tail of
+  // the launch balanced while the counter sees few requests.  Under a stop
+  // rule the items of stopped pairs cost nothing and waves running through
+  // them would queue on a counter, so those launches keep the plain walk.
+  // The last wave of the XCD to run out resets the counters for the next
+  // launch.
   const int xcd = blockIdx.x & 7;
   const int waves = (int)((gridDim.x - xcd + 7) >> 3) * NW;  // this XCD's waves
   const int widx = (int)(blockIdx.x >> 3) * NW + wave;       // this wave among them
