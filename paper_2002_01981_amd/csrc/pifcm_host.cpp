@@ -1180,9 +1180,11 @@ pifcm_status swarm_core(pifcm_ctx* ctx, const pifcm_volume* vols, int32_t B, con
   }
   const size_t npairs = (size_t)B * P;
   // Work items are numbered in 32 bits (their memberships alone would
-  // outgrow the device long before).
-  if (slots > (size_t)INT32_MAX)
-    return fail(ctx, PIFCM_E_UNSUPPORTED, "%zu tiles in one launch: more than 2^31", slots);
+  // outgrow the device long before), with room above the last one for the
+  // fused step's hand-out, whose final tickets run up to one per wave past
+  // the end of a range.
+  if (slots > (size_t)INT32_MAX - ((size_t)1 << 20))
+    return fail(ctx, PIFCM_E_UNSUPPORTED, "%zu tiles in one launch: more than 2^31 - 2^20", slots);
   TRY(ensure(ctx, ctx->ubuf, ubytes, "swarm memberships"));
   TRY(ensure(ctx, ctx->partials, slots * (2 * C + 1) * sizeof(float), "tile sums"));
   TRY(ensure(ctx, ctx->states, npairs * sizeof(SolveState), "solve states"));
